@@ -1,0 +1,235 @@
+/*
+ * bpmf.h -- C ABI of the MI355X (gfx950) BPMF Gibbs row-update library.
+ *
+ * The method: Bayesian probabilistic matrix factorisation sampled with Gibbs
+ * sweeps (paper: Section 2 "BPMF" and Algorithm 1).  The rating matrix R
+ * (M users x N movies, very sparse) is approximated by U V^T with U (M x K)
+ * and V (N x K) (Section 1).  Every sweep draws the hyper-parameters of one
+ * side from that side's factor matrix, then redraws every row of that side
+ * from its Gaussian conditional given the other side and its ratings, then
+ * does the same for the other side, then predicts the test points.  The row
+ * draw builds the K x K precision from the prior plus the outer products of
+ * the rated items' factor rows and factors it with a Cholesky decomposition
+ * instead of inverting it, because it is used only once (Section 3.1).
+ *
+ * Conventions of this library (the paper prints no formula):
+ *   row i:  P = Lambda + alpha sum_{j in Omega_i} v_j v_j^T,
+ *           b = Lambda mu + alpha sum_{j in Omega_i} (r_ij - rbar) v_j,
+ *           L L^T = P (lower, positive diagonal), x_i = L^{-T}(L^{-1} b + z_i)
+ *   side:   (mu, Lambda) ~ Normal-Wishart posterior with xbar, centred scatter
+ *           S, beta* = beta0 + n, nu* = nu0 + n, mu* = (beta0 mu0 + n xbar)/beta*,
+ *           W*^{-1} = W0^{-1} + S + beta0 n / beta* (xbar - mu0)(xbar - mu0)^T,
+ *           Lambda = L_W A A^T L_W^T (Bartlett, L_W = chol(W*)),
+ *           mu = mu* + chol(beta* Lambda)^{-T} z.
+ *   sweep:  users' half first, then movies'; hypers of a side come from that
+ *           side's current matrix.
+ *
+ * Memory: every pointer named d_* is device memory owned by the caller, who
+ * keeps it alive for the lifetime of the context that uses it.  The library
+ * allocates no device memory for a sampler: scratch comes from the caller's
+ * workspace (size from bpmf_workspace_size).  Host pointers (h_*, and the
+ * mu0 / W0 members of bpmf_params) are read during the call only.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the legacy
+ * default stream).  Calls enqueue work and return; results are ready when
+ * the stream is synchronised, unless stated otherwise.
+ *
+ * Errors: every function returns a bpmf_status and never aborts or throws.
+ * bpmf_last_error() gives a thread-local message for the last failure.
+ * Invalid arguments are rejected before any device work is enqueued.
+ */
+#ifndef BPMF_H
+#define BPMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BPMF_OK = 0,
+    BPMF_E_INVALID = 1,   /* bad argument: shapes, pointers, CSR/CSC structure, parameters */
+    BPMF_E_NOT_SPD = 2,   /* W0 (or a stored precision) is not symmetric positive definite */
+    BPMF_E_WORKSPACE = 3, /* workspace missing or smaller than required */
+    BPMF_E_STATE = 4,     /* context unusable (NULL, destroyed, or a previous fatal error) */
+    BPMF_E_HIP = 5,       /* a HIP runtime call or kernel launch failed */
+    BPMF_E_NOMEM = 6      /* host allocation failed */
+} bpmf_status;
+
+/* Arithmetic of the row update.
+ *   BPMF_FP64: everything in FP64; U and V are double.
+ *   BPMF_FP32: FP32 gathers, FP32 Gram on matrix cores, FP32 Cholesky; U, V float.
+ *   BPMF_BF16: BF16 copies of U and V are gathered; Gram on BF16 matrix cores
+ *              with FP32 accumulation; FP32 Cholesky; U, V float.
+ * In FP32/BF16 a row whose FP32 Cholesky pivot is not finite or falls below
+ * 64 K 2^-24 max_k P_kk is recomputed from the FP32 factors in FP64.
+ * The hyper-parameter step is always FP64. */
+typedef enum { BPMF_FP64 = 0, BPMF_FP32 = 1, BPMF_BF16 = 2 } bpmf_precision;
+
+/* Rating matrix in both orientations (Section 1: R is M x N, sparse).
+ * CSR: row_ptr[M+1] (int64, row_ptr[0] = 0, nondecreasing, row_ptr[M] = nnz),
+ *      col_idx[nnz] (int32, strictly increasing within a row, in [0, N)),
+ *      row_val[nnz].
+ * CSC: the same matrix by columns: col_ptr[N+1], row_idx[nnz], col_val[nnz].
+ * All device pointers.  val_is_f64 = 1: values are double, 0: float. */
+typedef struct {
+    int64_t M, N, nnz;
+    const int64_t *d_row_ptr;
+    const int32_t *d_col_idx;
+    const void *d_row_val;
+    const int64_t *d_col_ptr;
+    const int32_t *d_row_idx;
+    const void *d_col_val;
+    int32_t val_is_f64;
+} bpmf_ratings;
+
+/* Model and run parameters (Section 2: Gaussian rows, Normal-Wishart hyperpriors).
+ *   K          latent dimension, 1..128
+ *   precision  bpmf_precision
+ *   alpha      rating precision, > 0 (fixed, not sampled)
+ *   beta0      > 0; nu0 > K - 1; mu0[K] and W0[K*K] (row-major, SPD) host pointers
+ *   mean_rating  rbar subtracted from ratings and added to predictions;
+ *                NaN = the FP64 mean of the stored values (computed at init)
+ *   seed       key of the device counter-based generator (Philox4x32-10)
+ *   burnin     sweeps before test predictions are averaged
+ *   use_graph  1 = replay whole sweeps from a captured HIP graph (Philox mode)
+ *   validate   1 = copy CSR/CSC to the host at init and check the structure
+ *              (monotone pointers, sorted unique in-range indices, CSR == CSC) */
+typedef struct {
+    int32_t K;
+    int32_t precision;
+    double alpha;
+    double beta0;
+    double nu0;
+    const double *mu0;
+    const double *W0;
+    double mean_rating;
+    uint64_t seed;
+    int32_t burnin;
+    int32_t use_graph;
+    int32_t validate;
+} bpmf_params;
+
+typedef struct bpmf_ctx bpmf_ctx;
+
+/* Bytes of device workspace bpmf_init needs for this problem (including the
+ * running sums of n_test held-out predictions). */
+bpmf_status bpmf_workspace_size(const bpmf_ratings *R, const bpmf_params *p, int64_t n_test,
+                                size_t *bytes);
+
+/* Creates a sampler.  d_U (M x K) and d_V (N x K), row-major, hold the initial
+ * state and always the current sample afterwards: double in BPMF_FP64, float
+ * otherwise.  d_ws is the caller's workspace of ws_bytes.  n_test held-out
+ * pairs (d_test_rows, d_test_cols, int32, device) get a running mean of their
+ * predictions over sweeps >= burnin.  Errors: BPMF_E_INVALID (shapes, ranges,
+ * CSR/CSC structure when validate = 1), BPMF_E_NOT_SPD (W0),
+ * BPMF_E_WORKSPACE, BPMF_E_HIP.  Synchronises `stream` before returning. */
+bpmf_status bpmf_init(bpmf_ctx **ctx, const bpmf_ratings *R, const bpmf_params *p, void *d_U,
+                      void *d_V, void *d_ws, size_t ws_bytes, int64_t n_test,
+                      const int32_t *d_test_rows, const int32_t *d_test_cols, void *stream);
+
+/* Runs n_sweeps Gibbs sweeps (Algorithm 1).  d_tape = NULL: draws come from
+ * the device counter-based generator keyed by (seed, sweep, side, row).
+ * Otherwise d_tape (device, double) holds the draws of exactly these sweeps:
+ * per half-sweep over n rows (users' half first) K chi-square draws with
+ * nu0 + n - k degrees of freedom (k = 0..K-1), K(K-1)/2 Bartlett normals
+ * (row-major strict lower part), K mean normals, then n*K row normals
+ * (row-major); tape_len must equal n_sweeps times that count for both halves.
+ * Errors: BPMF_E_STATE, BPMF_E_INVALID (tape length), BPMF_E_HIP. */
+bpmf_status bpmf_sweep(bpmf_ctx *ctx, int32_t n_sweeps, const double *d_tape, int64_t tape_len,
+                       void *stream);
+
+/* Predictions u_i . v_j + rbar of the current sample for n pairs (device
+ * int32 rows/cols, device double output).  Errors: BPMF_E_INVALID if n < 0 or
+ * pointers are NULL with n > 0 (indices are range-checked only when
+ * validate = 1, on the host). */
+bpmf_status bpmf_predict(bpmf_ctx *ctx, int64_t n, const int32_t *d_rows, const int32_t *d_cols,
+                         double *d_out, void *stream);
+
+/* Running posterior-mean predictions of the held-out pairs given at init
+ * (device double[n_test]); *h_count (host) receives how many sweeps entered
+ * the mean.  Synchronises `stream`. */
+bpmf_status bpmf_test_predictions(bpmf_ctx *ctx, double *d_mean, int64_t *h_count, void *stream);
+
+/* Current hyper-parameters, synchronously copied to host memory:
+ * h_out[2 K^2 + 2 K] = [Lambda_U (K x K), mu_U, Lambda_V (K x K), mu_V], FP64. */
+bpmf_status bpmf_get_hyper(bpmf_ctx *ctx, double *h_out, void *stream);
+
+typedef struct {
+    int64_t sweeps_done;
+    int64_t fallback_rows; /* rows recomputed in FP64 since init (FP32/BF16 modes) */
+    int64_t nonfinite_rows;/* rows whose FP64 draw was not finite since init */
+    double mean_rating;
+    int32_t K, precision;
+} bpmf_info;
+
+/* Counters; synchronises `stream`. */
+bpmf_status bpmf_get_info(bpmf_ctx *ctx, bpmf_info *info, void *stream);
+
+/* Copies the current movie factors (as float, N x K) and the user-side
+ * hyper-parameters (Lambda_U as double K x K, mu_U as double K) into a
+ * caller-owned fold-in sample slot (device pointers). */
+bpmf_status bpmf_snapshot(bpmf_ctx *ctx, float *d_V_slot, double *d_Lambda_slot,
+                          double *d_mu_slot, void *stream);
+
+/* Saved sampler state: sweep counter, U, V, hypers and prediction sums.
+ * bpmf_state_size gives the bytes; save/restore use host memory and
+ * synchronise `stream`.  A restored context continues bit-identically. */
+bpmf_status bpmf_state_size(bpmf_ctx *ctx, size_t *bytes);
+bpmf_status bpmf_state_save(bpmf_ctx *ctx, void *h_buf, size_t bytes, void *stream);
+bpmf_status bpmf_state_restore(bpmf_ctx *ctx, const void *h_buf, size_t bytes, void *stream);
+
+/* Releases the context (host objects and graphs only). NULL is ignored. */
+bpmf_status bpmf_destroy(bpmf_ctx *ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Fold-in: conditional means of new users against stored posterior samples */
+/* ------------------------------------------------------------------------ */
+
+/* S stored samples of the movie factors and the user hypers:
+ *   d_V[S][N][K] float, d_Lambda[S][K][K] double (SPD), d_mu[S][K] double. */
+typedef struct {
+    int32_t S, K;
+    int64_t N;
+    double alpha;
+    double mean_rating;
+    const float *d_V;
+    const double *d_Lambda;
+    const double *d_mu;
+} bpmf_foldin_model;
+
+/* Bytes of workspace bpmf_foldin needs for a batch with n_queries query
+ * columns in total (S * n_queries floats of per-sample partial predictions). */
+bpmf_status bpmf_foldin_workspace_size(const bpmf_foldin_model *m, int64_t n_queries,
+                                       size_t *bytes);
+
+/* For each request r (ratings d_cols/d_vals[d_req_ptr[r] .. d_req_ptr[r+1]),
+ * query columns d_q_cols[d_q_ptr[r] .. d_q_ptr[r+1]), d_q_ptr[n_req] =
+ * n_queries) and each sample s:
+ *   m_s = (Lambda_s + alpha sum_j v_j v_j^T)^{-1}(Lambda_s mu_s + alpha sum_j (r_j - rbar) v_j)
+ * with v_j rows of sample s, and d_out[q] = rbar + (1/S) sum_s m_s . v_q (FP32
+ * arithmetic, samples summed in order).  Stateless: calls on different
+ * streams with different workspaces may overlap.  Each request's result does
+ * not depend on the other requests in the batch.  Errors: BPMF_E_INVALID,
+ * BPMF_E_WORKSPACE, BPMF_E_HIP.  K must be <= 64.  A sample whose FP32
+ * Cholesky pivot fails yields NaN predictions for that request. */
+bpmf_status bpmf_foldin(const bpmf_foldin_model *m, int64_t n_req, const int64_t *d_req_ptr,
+                        const int32_t *d_cols, const float *d_vals, const int64_t *d_q_ptr,
+                        const int32_t *d_q_cols, int64_t n_queries, float *d_out, void *d_ws,
+                        size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Misc                                                                      */
+/* ------------------------------------------------------------------------ */
+const char *bpmf_status_string(bpmf_status s);
+const char *bpmf_last_error(void);
+/* Library version string. */
+const char *bpmf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPMF_H */

@@ -1,0 +1,678 @@
+// bpmf_host.hip -- implementation of the C ABI declared in include/bpmf.h.
+//
+// Host-side plan of a sampler: validates the problem, carves the caller's
+// workspace, orders rows by rating count, and enqueues per sweep (paper:
+// Algorithm 1, users' half first):
+//   stats(U) -> hyper(U) -> rows(U | V) [-> FP64 recompute of flagged rows]
+//   stats(V) -> hyper(V) -> rows(V | U) [-> ...] -> predictions -> counter
+// With a device generator the whole sweep can be captured once as a HIP
+// graph and replayed; the kernels read the sweep counter from device memory.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/bpmf.h"
+#include "common.hpp"
+
+namespace bpmf {
+size_t rows_f64_lds_bytes(int K);
+hipError_t launch_advance_burnin(DevState *state, int burnin, hipStream_t s);
+hipError_t launch_foldin(int S, int K, int64_t N, double alpha, double rbar, const float *Vs,
+                         const double *Lam, const double *mu, int64_t n_req, const int64_t *req_ptr,
+                         const int32_t *cols, const float *vals, const int64_t *q_ptr,
+                         const int32_t *q_cols, int64_t n_queries, float *partial, float *out,
+                         hipStream_t st);
+hipError_t launch_sum_values(const void *vals, int is_f64, int64_t n, double *partials, int nblk,
+                             hipStream_t s);
+hipError_t launch_mean_from_sum(const double *accum, int64_t n, const DevState *state, double *out,
+                                hipStream_t s);
+hipError_t prepare_rows_f64(int K);
+hipError_t prepare_nw(int K);
+}  // namespace bpmf
+
+using namespace bpmf;
+
+static thread_local std::string g_last_error;
+
+static bpmf_status fail(bpmf_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_OK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return fail(BPMF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));    \
+    } while (0)
+
+static const size_t kAlign = 256;
+
+struct WsLayout {
+    size_t total = 0;
+    size_t add(size_t bytes)
+    {
+        size_t off = (total + kAlign - 1) / kAlign * kAlign;
+        total = off + bytes;
+        return off;
+    }
+};
+
+struct Offsets {
+    size_t state, partials[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], mu0, w0inv,
+        order[2], fblist[2], shadow[2], valsf[2], accum, reduce;
+    size_t total;
+};
+
+static int padded_k(int K) { return K <= 32 ? 32 : 64; }
+
+static bool mixed_supported(int K) { return K <= 64; }
+
+static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_test)
+{
+    Offsets o;
+    WsLayout w;
+    const int K = p->K;
+    const int64_t n[2] = {R->M, R->N};
+    const bool mixed = p->precision != BPMF_FP64;
+    const bool mk = mixed && mixed_supported(K);
+    o.state = w.add(sizeof(DevState));
+    for (int s = 0; s < 2; ++s) {
+        const int nc = stats_chunks(n[s]);
+        o.partials[s] = w.add(sizeof(double) * (size_t)nc * (K + K * (K + 1) / 2));
+        o.scratch[s] = w.add(sizeof(double) * nw_scratch_doubles(K));
+        o.lam[s] = w.add(sizeof(double) * K * K);
+        o.mu[s] = w.add(sizeof(double) * K);
+        o.lmu[s] = w.add(sizeof(double) * K);
+        o.lamf[s] = w.add(sizeof(float) * K * K);
+        o.lmuf[s] = w.add(sizeof(float) * K);
+        o.order[s] = w.add(sizeof(int32_t) * n[s]);
+        o.fblist[s] = w.add(mk ? sizeof(int32_t) * n[s] : 0);
+        o.shadow[s] = w.add((mk && p->precision == BPMF_BF16) ? sizeof(uint16_t) * n[s] * padded_k(K) : 0);
+        o.valsf[s] = w.add((mixed && R->val_is_f64) ? sizeof(float) * R->nnz : 0);
+    }
+    o.mu0 = w.add(sizeof(double) * K);
+    o.w0inv = w.add(sizeof(double) * K * K);
+    o.accum = w.add(sizeof(double) * std::max<int64_t>(n_test, 0));
+    o.reduce = w.add(sizeof(double) * 1024);
+    o.total = w.total + kAlign;
+    return o;
+}
+
+struct bpmf_ctx {
+    bpmf_ratings R;
+    int K, KP, precision, burnin, use_graph;
+    double alpha, beta0, nu0, rbar;
+    uint64_t seed;
+    void *dU, *dV;
+    char *ws;
+    Offsets off;
+    DevState *state;
+    HyperDev hyp[2];
+    int n_chunks[2];
+    int64_t n_test;
+    const int32_t *test_rows, *test_cols;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    bool broken = false;
+    bool x_f64() const { return precision == BPMF_FP64; }
+    template <class T> T *at(size_t o) const { return (T *)(ws + o); }
+};
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+static bool host_cholesky(int n, const std::vector<double> &A, std::vector<double> &L)
+{
+    L.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            if (i == j) {
+                if (!(s > 0.0) || !std::isfinite(s)) return false;
+                L[(size_t)i * n + i] = std::sqrt(s);
+            } else {
+                L[(size_t)i * n + j] = s / L[(size_t)j * n + j];
+            }
+        }
+    return true;
+}
+
+static bool host_spd_inverse(int n, const std::vector<double> &A, std::vector<double> &inv)
+{
+    std::vector<double> L;
+    if (!host_cholesky(n, A, L)) return false;
+    // inv = L^{-T} L^{-1}; first Li = L^{-1}
+    std::vector<double> Li((size_t)n * n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        Li[(size_t)c * n + c] = 1.0 / L[(size_t)c * n + c];
+        for (int i = c + 1; i < n; ++i) {
+            double s = 0.0;
+            for (int m = c; m < i; ++m) s += L[(size_t)i * n + m] * Li[(size_t)m * n + c];
+            Li[(size_t)i * n + c] = -s / L[(size_t)i * n + i];
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    for (int a = 0; a < n; ++a)
+        for (int c = 0; c <= a; ++c) {
+            double s = 0.0;
+            for (int m = a; m < n; ++m) s += Li[(size_t)m * n + a] * Li[(size_t)m * n + c];
+            inv[(size_t)a * n + c] = s;
+            inv[(size_t)c * n + a] = s;
+        }
+    return true;
+}
+
+static bpmf_status check_params(const bpmf_ratings *R, const bpmf_params *p)
+{
+    if (!R || !p) return fail(BPMF_E_INVALID, "NULL ratings or params");
+    if (p->K < 1 || p->K > 128) return fail(BPMF_E_INVALID, "K must be in 1..128");
+    if (p->precision < BPMF_FP64 || p->precision > BPMF_BF16)
+        return fail(BPMF_E_INVALID, "unknown precision");
+    if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return fail(BPMF_E_INVALID, "alpha must be > 0");
+    if (!(p->beta0 > 0.0) || !std::isfinite(p->beta0)) return fail(BPMF_E_INVALID, "beta0 must be > 0");
+    if (!(p->nu0 > p->K - 1) || !std::isfinite(p->nu0)) return fail(BPMF_E_INVALID, "nu0 must be > K - 1");
+    if (!p->mu0 || !p->W0) return fail(BPMF_E_INVALID, "mu0 and W0 are required");
+    if (p->burnin < 0) return fail(BPMF_E_INVALID, "burnin must be >= 0");
+    if (R->M < 1 || R->N < 1 || R->nnz < 0) return fail(BPMF_E_INVALID, "M, N must be >= 1, nnz >= 0");
+    if (R->M > INT32_MAX || R->N > INT32_MAX) return fail(BPMF_E_INVALID, "M and N must fit in int32");
+    if (!R->d_row_ptr || !R->d_col_ptr) return fail(BPMF_E_INVALID, "NULL row_ptr/col_ptr");
+    if (R->nnz > 0 && (!R->d_col_idx || !R->d_row_val || !R->d_row_idx || !R->d_col_val))
+        return fail(BPMF_E_INVALID, "NULL index or value array");
+    for (int i = 0; i < p->K; ++i)
+        if (!std::isfinite(p->mu0[i])) return fail(BPMF_E_INVALID, "mu0 not finite");
+    for (int i = 0; i < p->K; ++i)
+        for (int j = 0; j < p->K; ++j)
+            if (p->W0[(size_t)i * p->K + j] != p->W0[(size_t)j * p->K + i])
+                return fail(BPMF_E_NOT_SPD, "W0 is not symmetric");
+    std::vector<double> W(p->W0, p->W0 + (size_t)p->K * p->K), L;
+    if (!host_cholesky(p->K, W, L)) return fail(BPMF_E_NOT_SPD, "W0 is not positive definite");
+    return BPMF_OK;
+}
+
+static bool check_structure(const std::vector<int64_t> &ptr, const std::vector<int32_t> &idx,
+                            int64_t n_other, std::string &why)
+{
+    if (ptr[0] != 0) { why = "pointer array must start at 0"; return false; }
+    for (size_t i = 0; i + 1 < ptr.size(); ++i) {
+        if (ptr[i + 1] < ptr[i]) { why = "pointer array decreases at " + std::to_string(i); return false; }
+        for (int64_t t = ptr[i]; t < ptr[i + 1]; ++t) {
+            if (idx[t] < 0 || idx[t] >= n_other) { why = "index out of range in row " + std::to_string(i); return false; }
+            if (t > ptr[i] && idx[t] <= idx[t - 1]) { why = "indices not strictly increasing in row " + std::to_string(i); return false; }
+        }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *bpmf_status_string(bpmf_status s)
+{
+    switch (s) {
+    case BPMF_OK: return "ok";
+    case BPMF_E_INVALID: return "invalid argument";
+    case BPMF_E_NOT_SPD: return "matrix not symmetric positive definite";
+    case BPMF_E_WORKSPACE: return "workspace too small";
+    case BPMF_E_STATE: return "invalid context state";
+    case BPMF_E_HIP: return "HIP runtime error";
+    case BPMF_E_NOMEM: return "host allocation failed";
+    }
+    return "unknown status";
+}
+
+const char *bpmf_last_error(void) { return g_last_error.c_str(); }
+
+const char *bpmf_version(void) { return "bpmf-gfx950 0.1"; }
+
+bpmf_status bpmf_workspace_size(const bpmf_ratings *R, const bpmf_params *p, int64_t n_test, size_t *bytes)
+{
+    bpmf_status st = check_params(R, p);
+    if (st != BPMF_OK) return st;
+    if (!bytes) return fail(BPMF_E_INVALID, "NULL bytes");
+    if (n_test < 0) return fail(BPMF_E_INVALID, "n_test < 0");
+    *bytes = layout(R, p, n_test).total;
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *p, void *d_U,
+                      void *d_V, void *d_ws, size_t ws_bytes, int64_t n_test,
+                      const int32_t *d_test_rows, const int32_t *d_test_cols, void *stream)
+{
+    if (!out) return fail(BPMF_E_INVALID, "NULL ctx output");
+    *out = nullptr;
+    bpmf_status st = check_params(R, p);
+    if (st != BPMF_OK) return st;
+    if (!d_U || !d_V) return fail(BPMF_E_INVALID, "NULL U or V");
+    if (n_test < 0 || (n_test > 0 && (!d_test_rows || !d_test_cols)))
+        return fail(BPMF_E_INVALID, "bad test set");
+    Offsets off = layout(R, p, n_test);
+    if (!d_ws || ws_bytes < off.total)
+        return fail(BPMF_E_WORKSPACE, "workspace needs " + std::to_string(off.total) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    const int K = p->K;
+    const int64_t n[2] = {R->M, R->N};
+
+    // structure: pointer arrays always, indices when asked
+    std::vector<int64_t> ptr[2] = {std::vector<int64_t>(R->M + 1), std::vector<int64_t>(R->N + 1)};
+    HIP_OK(hipMemcpyAsync(ptr[0].data(), R->d_row_ptr, sizeof(int64_t) * (R->M + 1), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ptr[1].data(), R->d_col_ptr, sizeof(int64_t) * (R->N + 1), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int sd = 0; sd < 2; ++sd) {
+        if (ptr[sd][0] != 0 || ptr[sd][n[sd]] != R->nnz)
+            return fail(BPMF_E_INVALID, "pointer array must run from 0 to nnz");
+        for (int64_t i = 0; i < n[sd]; ++i)
+            if (ptr[sd][i + 1] < ptr[sd][i]) return fail(BPMF_E_INVALID, "pointer array decreases");
+    }
+    if (p->validate && R->nnz > 0) {
+        std::vector<int32_t> ci(R->nnz), ri(R->nnz);
+        const size_t vb = R->val_is_f64 ? 8 : 4;
+        std::vector<char> rv(R->nnz * vb), cv(R->nnz * vb);
+        HIP_OK(hipMemcpyAsync(ci.data(), R->d_col_idx, 4 * R->nnz, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(ri.data(), R->d_row_idx, 4 * R->nnz, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(rv.data(), R->d_row_val, vb * R->nnz, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(cv.data(), R->d_col_val, vb * R->nnz, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        std::string why;
+        if (!check_structure(ptr[0], ci, R->N, why)) return fail(BPMF_E_INVALID, "CSR: " + why);
+        if (!check_structure(ptr[1], ri, R->M, why)) return fail(BPMF_E_INVALID, "CSC: " + why);
+        // CSR == CSC: walk CSR in column-major order via per-column cursors
+        std::vector<int64_t> cur(ptr[1].begin(), ptr[1].end() - 1);
+        for (int64_t i = 0; i < R->M; ++i)
+            for (int64_t t = ptr[0][i]; t < ptr[0][i + 1]; ++t) {
+                const int64_t c = ci[t];
+                const int64_t u = cur[c]++;
+                if (u >= ptr[1][c + 1] || ri[u] != i || std::memcmp(&rv[t * vb], &cv[u * vb], vb) != 0)
+                    return fail(BPMF_E_INVALID, "CSR and CSC differ at row " + std::to_string(i));
+            }
+        for (int64_t t = 0; t < R->nnz; ++t) {
+            double x = R->val_is_f64 ? ((double *)rv.data())[t] : ((float *)rv.data())[t];
+            if (!std::isfinite(x)) return fail(BPMF_E_INVALID, "non-finite rating value");
+        }
+    }
+
+    bpmf_ctx *c = new (std::nothrow) bpmf_ctx();
+    if (!c) return fail(BPMF_E_NOMEM, "context allocation");
+    c->R = *R;
+    c->K = K;
+    c->KP = padded_k(K);
+    c->precision = p->precision;
+    c->burnin = p->burnin;
+    c->use_graph = p->use_graph;
+    c->alpha = p->alpha;
+    c->beta0 = p->beta0;
+    c->nu0 = p->nu0;
+    c->seed = p->seed;
+    c->dU = d_U;
+    c->dV = d_V;
+    c->ws = (char *)(((uintptr_t)d_ws + kAlign - 1) / kAlign * kAlign);
+    c->off = off;
+    c->state = c->at<DevState>(off.state);
+    c->n_test = n_test;
+    c->test_rows = d_test_rows;
+    c->test_cols = d_test_cols;
+    for (int sd = 0; sd < 2; ++sd) {
+        c->n_chunks[sd] = stats_chunks(n[sd]);
+        c->hyp[sd].Lambda = c->at<double>(off.lam[sd]);
+        c->hyp[sd].mu = c->at<double>(off.mu[sd]);
+        c->hyp[sd].Lmu = c->at<double>(off.lmu[sd]);
+        c->hyp[sd].Lambda_f = c->at<float>(off.lamf[sd]);
+        c->hyp[sd].Lmu_f = c->at<float>(off.lmuf[sd]);
+    }
+    auto bail = [&](bpmf_status e) { delete c; return e; };
+#define HIP_OK_C(expr)                                                                      \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess) return bail(fail(BPMF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e))); \
+    } while (0)
+
+    HIP_OK_C(prepare_rows_f64(K));
+    HIP_OK_C(prepare_nw(K));
+    HIP_OK_C(launch_fill_zero(c->ws, off.total - kAlign, s));
+
+    // mean rating
+    double rbar = p->mean_rating;
+    if (std::isnan(rbar)) {
+        if (R->nnz == 0) {
+            rbar = 0.0;
+        } else {
+            const int nblk = 1024;
+            HIP_OK_C(launch_sum_values(R->d_row_val, R->val_is_f64, R->nnz, c->at<double>(off.reduce), nblk, s));
+            std::vector<double> part(nblk);
+            HIP_OK_C(hipMemcpyAsync(part.data(), c->at<double>(off.reduce), sizeof(double) * nblk, hipMemcpyDeviceToHost, s));
+            HIP_OK_C(hipStreamSynchronize(s));
+            double sum = 0.0;
+            for (double v : part) sum += v;
+            rbar = sum / (double)R->nnz;
+        }
+    }
+    c->rbar = rbar;
+
+    // row order: rating count descending, ties by index
+    for (int sd = 0; sd < 2; ++sd) {
+        std::vector<int32_t> ord(n[sd]);
+        std::iota(ord.begin(), ord.end(), 0);
+        const std::vector<int64_t> &pp = ptr[sd];
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+            return pp[a + 1] - pp[a] > pp[b + 1] - pp[b];
+        });
+        HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.order[sd]), ord.data(), sizeof(int32_t) * n[sd], hipMemcpyHostToDevice, s));
+        HIP_OK_C(hipStreamSynchronize(s));
+    }
+    // priors
+    std::vector<double> W0(p->W0, p->W0 + (size_t)K * K), W0inv;
+    if (!host_spd_inverse(K, W0, W0inv)) return bail(fail(BPMF_E_NOT_SPD, "W0 is not positive definite"));
+    HIP_OK_C(hipMemcpyAsync(c->at<double>(off.mu0), p->mu0, sizeof(double) * K, hipMemcpyHostToDevice, s));
+    HIP_OK_C(hipMemcpyAsync(c->at<double>(off.w0inv), W0inv.data(), sizeof(double) * K * K, hipMemcpyHostToDevice, s));
+    // FP32 copies of the ratings for the mixed kernels
+    if (p->precision != BPMF_FP64 && R->val_is_f64) {
+        HIP_OK_C(launch_f64_to_f32((const double *)R->d_row_val, c->at<float>(off.valsf[0]), R->nnz, s));
+        HIP_OK_C(launch_f64_to_f32((const double *)R->d_col_val, c->at<float>(off.valsf[1]), R->nnz, s));
+    }
+    // BF16 copies of the initial factors
+    if (p->precision == BPMF_BF16 && mixed_supported(K)) {
+        HIP_OK_C(launch_to_bf16((const float *)d_U, R->M, K, c->KP, c->at<uint16_t>(off.shadow[0]), s));
+        HIP_OK_C(launch_to_bf16((const float *)d_V, R->N, K, c->KP, c->at<uint16_t>(off.shadow[1]), s));
+    }
+    HIP_OK_C(hipStreamSynchronize(s));
+#undef HIP_OK_C
+    *out = c;
+    return BPMF_OK;
+}
+
+}  // extern "C"
+
+// One half-sweep on stream s.
+static bpmf_status enqueue_half(bpmf_ctx *c, int side, const double *tape_block, hipStream_t s)
+{
+    const int K = c->K;
+    const bpmf_ratings &R = c->R;
+    const int64_t n = side == 0 ? R.M : R.N;
+    void *X = side == 0 ? c->dU : c->dV;
+    void *other = side == 0 ? c->dV : c->dU;
+    const bool f64 = c->precision == BPMF_FP64;
+    const bool mixed_kernel = !f64 && mixed_supported(K);
+    DrawSrc d;
+    d.tape_nw = tape_block;
+    d.tape_rows = tape_block ? tape_block + K + K * (K - 1) / 2 + K : nullptr;
+    d.seed = c->seed;
+    d.sweep = &c->state->sweep;
+    d.side = side;
+
+    HIP_OK(launch_stats(X, f64 ? 1 : 0, n, K, c->at<double>(c->off.partials[side]), c->n_chunks[side], s));
+    HIP_OK(launch_nw(c->at<double>(c->off.partials[side]), c->n_chunks[side], n, K, c->at<double>(c->off.mu0),
+                     c->beta0, c->nu0, c->at<double>(c->off.w0inv), d, c->at<double>(c->off.scratch[side]),
+                     c->hyp[side], K <= 64 ? 1 : 0, s));
+
+    SideArgs a;
+    a.n_rows = n;
+    a.ptr = side == 0 ? R.d_row_ptr : R.d_col_ptr;
+    a.idx = side == 0 ? R.d_col_idx : R.d_row_idx;
+    const void *vals_orig = side == 0 ? R.d_row_val : R.d_col_val;
+    a.X = X;
+    a.other = other;
+    a.order = c->at<int32_t>(c->off.order[side]);
+    a.shadow_stride = c->KP;
+    if (f64) {
+        a.val = vals_orig;
+        a.val_is_f64 = R.val_is_f64;
+        a.other_bf16 = nullptr;
+        a.X_bf16 = nullptr;
+        HIP_OK(launch_rows_f64(a, K, c->alpha, c->rbar, c->hyp[side], d, nullptr, nullptr, n, 0, c->state, s));
+        return BPMF_OK;
+    }
+    const bool bf16 = c->precision == BPMF_BF16 && mixed_kernel;
+    a.val = R.val_is_f64 ? (const void *)c->at<float>(c->off.valsf[side]) : vals_orig;
+    a.val_is_f64 = 0;
+    a.other_bf16 = bf16 ? c->at<uint16_t>(c->off.shadow[1 - side]) : nullptr;
+    a.X_bf16 = bf16 ? c->at<uint16_t>(c->off.shadow[side]) : nullptr;
+    if (!mixed_kernel) {
+        // K > 64: FP64 arithmetic on FP32 storage
+        HIP_OK(launch_rows_f64(a, K, c->alpha, c->rbar, c->hyp[side], d, nullptr, nullptr, n, 1, c->state, s));
+        return BPMF_OK;
+    }
+    HIP_OK(launch_reset_fallback(c->state, side, s));
+    HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d,
+                             c->at<int32_t>(c->off.fblist[side]), c->state, s));
+    HIP_OK(launch_rows_f64(a, K, c->alpha, c->rbar, c->hyp[side], d, c->at<int32_t>(c->off.fblist[side]),
+                           &c->state->fb_count[side], n, 1, c->state, s));
+    return BPMF_OK;
+}
+
+static bpmf_status enqueue_sweep(bpmf_ctx *c, const double *tape, hipStream_t s)
+{
+    const int K = c->K;
+    const int64_t hb = (int64_t)K + (int64_t)K * (K - 1) / 2 + K;
+    bpmf_status st = enqueue_half(c, 0, tape, s);
+    if (st != BPMF_OK) return st;
+    st = enqueue_half(c, 1, tape ? tape + hb + c->R.M * K : nullptr, s);
+    if (st != BPMF_OK) return st;
+    if (c->n_test > 0)
+        HIP_OK(launch_predict(c->dU, c->dV, c->x_f64() ? 1 : 0, K, c->rbar, c->n_test, c->test_rows,
+                              c->test_cols, nullptr, c->at<double>(c->off.accum), c->state, c->burnin, s));
+    HIP_OK(launch_advance_burnin(c->state, c->burnin, s));
+    return BPMF_OK;
+}
+
+extern "C" {
+
+bpmf_status bpmf_sweep(bpmf_ctx *c, int32_t n_sweeps, const double *d_tape, int64_t tape_len, void *stream)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (n_sweeps < 0) return fail(BPMF_E_INVALID, "n_sweeps < 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int K = c->K;
+    const int64_t hb = (int64_t)K + (int64_t)K * (K - 1) / 2 + K;
+    const int64_t sweep_len = 2 * hb + (c->R.M + c->R.N) * K;
+    if (d_tape) {
+        if (tape_len != (int64_t)n_sweeps * sweep_len)
+            return fail(BPMF_E_INVALID, "tape length " + std::to_string(tape_len) + " != " +
+                                            std::to_string((int64_t)n_sweeps * sweep_len));
+        for (int i = 0; i < n_sweeps; ++i) {
+            bpmf_status st = enqueue_sweep(c, d_tape + (int64_t)i * sweep_len, s);
+            if (st != BPMF_OK) { c->broken = true; return st; }
+        }
+        return BPMF_OK;
+    }
+    if (!c->use_graph) {
+        for (int i = 0; i < n_sweeps; ++i) {
+            bpmf_status st = enqueue_sweep(c, nullptr, s);
+            if (st != BPMF_OK) { c->broken = true; return st; }
+        }
+        return BPMF_OK;
+    }
+    if (!c->gexec) {
+        HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        bpmf_status st = enqueue_sweep(c, nullptr, c->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (st != BPMF_OK) { c->broken = true; return st; }
+        if (e != hipSuccess) { c->broken = true; return fail(BPMF_E_HIP, std::string("graph capture: ") + hipGetErrorString(e)); }
+        c->graph = g;
+        HIP_OK(hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+    }
+    for (int i = 0; i < n_sweeps; ++i) HIP_OK(hipGraphLaunch(c->gexec, s));
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_predict(bpmf_ctx *c, int64_t n, const int32_t *d_rows, const int32_t *d_cols, double *d_out, void *stream)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (n < 0 || (n > 0 && (!d_rows || !d_cols || !d_out))) return fail(BPMF_E_INVALID, "bad predict arguments");
+    HIP_OK(launch_predict(c->dU, c->dV, c->x_f64() ? 1 : 0, c->K, c->rbar, n, d_rows, d_cols, d_out, nullptr, c->state, 0, (hipStream_t)stream));
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_test_predictions(bpmf_ctx *c, double *d_mean, int64_t *h_count, void *stream)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n_test > 0) {
+        if (!d_mean) return fail(BPMF_E_INVALID, "NULL d_mean");
+        HIP_OK(launch_mean_from_sum(c->at<double>(c->off.accum), c->n_test, c->state, d_mean, s));
+    }
+    DevState h;
+    HIP_OK(hipMemcpyAsync(&h, c->state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (h_count) *h_count = h.pred_count;
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_get_hyper(bpmf_ctx *c, double *h_out, void *stream)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (!h_out) return fail(BPMF_E_INVALID, "NULL output");
+    hipStream_t s = (hipStream_t)stream;
+    const int K = c->K;
+    for (int sd = 0; sd < 2; ++sd) {
+        double *o = h_out + sd * (K * K + K);
+        HIP_OK(hipMemcpyAsync(o, c->hyp[sd].Lambda, sizeof(double) * K * K, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(o + K * K, c->hyp[sd].mu, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_get_info(bpmf_ctx *c, bpmf_info *info, void *stream)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (!info) return fail(BPMF_E_INVALID, "NULL info");
+    hipStream_t s = (hipStream_t)stream;
+    DevState h;
+    HIP_OK(hipMemcpyAsync(&h, c->state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    info->sweeps_done = h.sweep;
+    info->fallback_rows = h.fallback_rows;
+    info->nonfinite_rows = h.nonfinite_rows;
+    info->mean_rating = c->rbar;
+    info->K = c->K;
+    info->precision = c->precision;
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_snapshot(bpmf_ctx *c, float *d_V_slot, double *d_Lambda_slot, double *d_mu_slot, void *stream)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (!d_V_slot || !d_Lambda_slot || !d_mu_slot) return fail(BPMF_E_INVALID, "NULL slot");
+    hipStream_t s = (hipStream_t)stream;
+    const int K = c->K;
+    HIP_OK(launch_copy_f32_from(c->dV, c->x_f64() ? 1 : 0, c->R.N * K, d_V_slot, s));
+    HIP_OK(hipMemcpyAsync(d_Lambda_slot, c->hyp[0].Lambda, sizeof(double) * K * K, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(d_mu_slot, c->hyp[0].mu, sizeof(double) * K, hipMemcpyDeviceToDevice, s));
+    return BPMF_OK;
+}
+
+static size_t state_bytes(bpmf_ctx *c)
+{
+    const size_t xb = c->x_f64() ? 8 : 4;
+    const int K = c->K;
+    return sizeof(DevState) + xb * (size_t)(c->R.M + c->R.N) * K + 2 * sizeof(double) * (K * K + 2 * K) +
+           sizeof(double) * (size_t)c->n_test;
+}
+
+bpmf_status bpmf_state_size(bpmf_ctx *c, size_t *bytes)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (!bytes) return fail(BPMF_E_INVALID, "NULL bytes");
+    *bytes = state_bytes(c);
+    return BPMF_OK;
+}
+
+static bpmf_status state_copy(bpmf_ctx *c, char *h, bool save, hipStream_t s)
+{
+    const size_t xb = c->x_f64() ? 8 : 4;
+    const int K = c->K;
+    auto cp = [&](void *dev, size_t n) -> hipError_t {
+        hipError_t e = save ? hipMemcpyAsync(h, dev, n, hipMemcpyDeviceToHost, s)
+                            : hipMemcpyAsync(dev, h, n, hipMemcpyHostToDevice, s);
+        h += n;
+        return e;
+    };
+    HIP_OK(cp(c->state, sizeof(DevState)));
+    HIP_OK(cp(c->dU, xb * c->R.M * K));
+    HIP_OK(cp(c->dV, xb * c->R.N * K));
+    for (int sd = 0; sd < 2; ++sd) {
+        HIP_OK(cp(c->hyp[sd].Lambda, sizeof(double) * K * K));
+        HIP_OK(cp(c->hyp[sd].mu, sizeof(double) * K));
+        HIP_OK(cp(c->hyp[sd].Lmu, sizeof(double) * K));
+    }
+    if (c->n_test > 0) HIP_OK(cp(c->at<double>(c->off.accum), sizeof(double) * c->n_test));
+    if (!save) {
+        for (int sd = 0; sd < 2; ++sd) {
+            HIP_OK(launch_f64_to_f32(c->hyp[sd].Lambda, c->hyp[sd].Lambda_f, (int64_t)K * K, s));
+            HIP_OK(launch_f64_to_f32(c->hyp[sd].Lmu, c->hyp[sd].Lmu_f, K, s));
+        }
+        if (c->precision == BPMF_BF16 && mixed_supported(K)) {
+            HIP_OK(launch_to_bf16((const float *)c->dU, c->R.M, K, c->KP, c->at<uint16_t>(c->off.shadow[0]), s));
+            HIP_OK(launch_to_bf16((const float *)c->dV, c->R.N, K, c->KP, c->at<uint16_t>(c->off.shadow[1]), s));
+        }
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_state_save(bpmf_ctx *c, void *h_buf, size_t bytes, void *stream)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (!h_buf || bytes < state_bytes(c)) return fail(BPMF_E_INVALID, "state buffer too small");
+    return state_copy(c, (char *)h_buf, true, (hipStream_t)stream);
+}
+
+bpmf_status bpmf_state_restore(bpmf_ctx *c, const void *h_buf, size_t bytes, void *stream)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (!h_buf || bytes < state_bytes(c)) return fail(BPMF_E_INVALID, "state buffer too small");
+    return state_copy(c, (char *)h_buf, false, (hipStream_t)stream);
+}
+
+bpmf_status bpmf_destroy(bpmf_ctx *c)
+{
+    if (!c) return BPMF_OK;
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    delete c;
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_foldin_workspace_size(const bpmf_foldin_model *m, int64_t n_queries, size_t *bytes)
+{
+    if (!m || !bytes) return fail(BPMF_E_INVALID, "NULL argument");
+    if (m->S < 1 || n_queries < 0) return fail(BPMF_E_INVALID, "S must be >= 1, n_queries >= 0");
+    *bytes = sizeof(float) * (size_t)m->S * (size_t)std::max<int64_t>(n_queries, 1);
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_foldin(const bpmf_foldin_model *m, int64_t n_req, const int64_t *d_req_ptr,
+                        const int32_t *d_cols, const float *d_vals, const int64_t *d_q_ptr,
+                        const int32_t *d_q_cols, int64_t n_queries, float *d_out, void *d_ws,
+                        size_t ws_bytes, void *stream)
+{
+    if (!m) return fail(BPMF_E_INVALID, "NULL model");
+    if (m->S < 1 || m->K < 1 || m->K > 64 || m->N < 1) return fail(BPMF_E_INVALID, "fold-in needs S >= 1, 1 <= K <= 64, N >= 1");
+    if (!m->d_V || !m->d_Lambda || !m->d_mu) return fail(BPMF_E_INVALID, "NULL model arrays");
+    if (!(m->alpha > 0.0)) return fail(BPMF_E_INVALID, "alpha must be > 0");
+    if (n_req < 0 || n_queries < 0) return fail(BPMF_E_INVALID, "negative sizes");
+    if (n_req == 0) return BPMF_OK;
+    if (!d_req_ptr || !d_q_ptr || (n_queries > 0 && (!d_q_cols || !d_out)))
+        return fail(BPMF_E_INVALID, "NULL request arrays");
+    size_t need = 0;
+    bpmf_foldin_workspace_size(m, n_queries, &need);
+    if (!d_ws || ws_bytes < need) return fail(BPMF_E_WORKSPACE, "fold-in workspace needs " + std::to_string(need) + " bytes");
+    HIP_OK(launch_foldin(m->S, m->K, m->N, m->alpha, m->mean_rating, m->d_V, m->d_Lambda, m->d_mu, n_req,
+                         d_req_ptr, d_cols, d_vals, d_q_ptr, d_q_cols, n_queries, (float *)d_ws, d_out,
+                         (hipStream_t)stream));
+    return BPMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// common.hpp -- shared declarations of the HIP kernels and the host library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bpmf {
+
+// Where a half-sweep's standard normals come from: a tape block (row-major
+// n x K doubles) or the device counter-based generator at half-sweep
+// h = 2 * (*sweep) + side.
+struct DrawSrc {
+    const double *tape_rows;   // NULL -> counter-based generator
+    const double *tape_nw;     // [K chi2][K(K-1)/2 Bartlett][K mean normals] or NULL
+    uint64_t seed;
+    const int64_t *sweep;      // device sweep counter
+    int32_t side;              // 0 users, 1 movies
+};
+
+__device__ __forceinline__ uint32_t half_sweep_index(const DrawSrc &d)
+{
+    return (uint32_t)(2 * (*d.sweep) + d.side);
+}
+
+// Device-resident counters of a sampler.
+struct DevState {
+    int64_t sweep;            // sweeps completed
+    int64_t pred_count;       // sweeps entered into the test-prediction mean
+    int64_t fallback_rows;    // cumulative FP64 recomputes
+    int64_t nonfinite_rows;   // cumulative non-finite FP64 rows
+    int32_t fb_count[2];      // rows queued for FP64 recompute in the current half-sweep
+    int32_t pad[2];
+};
+
+// Hyper-parameters of one side, FP64 with FP32 copies for the mixed kernels.
+struct HyperDev {
+    double *Lambda;  // K x K
+    double *mu;      // K
+    double *Lmu;     // K  (Lambda mu)
+    float *Lambda_f; // K x K
+    float *Lmu_f;    // K
+};
+
+// One half-sweep: rows of one side against the other side's factors.
+struct SideArgs {
+    int64_t n_rows;
+    const int64_t *ptr;
+    const int32_t *idx;
+    const void *val;        // float or double ratings
+    int32_t val_is_f64;
+    const void *other;      // master of the other side (double in FP64 mode, else float)
+    const uint16_t *other_bf16;  // BF16 copy of the other side (row stride KP), BF16 mode
+    void *X;                // master of this side (output)
+    uint16_t *X_bf16;       // BF16 copy of this side (output), or NULL
+    int32_t shadow_stride;  // row stride of the BF16 copies
+    const int32_t *order;   // rows in processing order (nnz descending)
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) {  // inf or nan
+        return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h)
+{
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files; all return hipError_t of the launch)
+// ---------------------------------------------------------------------------
+hipError_t launch_stats(const void *X, int x_is_f64, int64_t n, int K, double *partials,
+                        int n_chunks, hipStream_t s);
+int stats_chunks(int64_t n);
+size_t nw_scratch_doubles(int K);
+hipError_t launch_nw(const double *partials, int n_chunks, int64_t n, int K, const double *mu0,
+                     double beta0, double nu0, const double *W0inv, DrawSrc draws,
+                     double *scratch, HyperDev hyp, int use_lds, hipStream_t s);
+hipError_t launch_rows_f64(const SideArgs &a, int K, double alpha, double rbar,
+                           HyperDev hyp, DrawSrc draws, const int32_t *list,
+                           const int32_t *list_count, int64_t max_rows, int x_is_f32,
+                           DevState *state, hipStream_t s);
+hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double alpha,
+                             double rbar, HyperDev hyp, DrawSrc draws, int32_t *fb_list,
+                             DevState *state, hipStream_t s);
+hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, double rbar,
+                          int64_t n, const int32_t *rows, const int32_t *cols, double *out,
+                          double *accum, const DevState *state, int burnin, hipStream_t s);
+hipError_t launch_advance_burnin(DevState *state, int burnin, hipStream_t s);
+hipError_t launch_reset_fallback(DevState *state, int side, hipStream_t s);
+hipError_t launch_to_bf16(const float *X, int64_t n, int K, int stride, uint16_t *out,
+                          hipStream_t s);
+hipError_t launch_f64_to_f32(const double *in, float *out, int64_t n, hipStream_t s);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_copy_f32_from(const void *X, int x_is_f64, int64_t n, float *out,
+                                hipStream_t s);
+
+}  // namespace bpmf

@@ -1,0 +1,493 @@
+// kernels_f64.hip -- the plain FP64 row update (one workgroup per row), the
+// side statistics for the hyper-parameter step, predictions and small helpers.
+//
+// Row update (paper: Section 2, Algorithm 1 inner loops; Section 3.1): for
+// row i with rated items Omega_i,
+//   P = Lambda + alpha sum_j v_j v_j^T,  b = Lambda mu + alpha sum_j (r_ij - rbar) v_j,
+//   L L^T = P,  x_i = L^{-T}(L^{-1} b + z_i).
+// This kernel keeps P in LDS (K <= 128: at most 128 KB of FP64), gathers the
+// rated rows in chunks of 16 into LDS, accumulates the lower triangle of the
+// Gram in 4x4 register tiles, factors P with a right-looking Cholesky across
+// the workgroup, and solves with one thread per element.
+#include <algorithm>
+
+#include "common.hpp"
+#include "rng.hpp"
+
+namespace bpmf {
+
+namespace {
+
+constexpr int F64_CH = 16;  // gathered rows per LDS chunk
+
+__device__ __forceinline__ void tri_decode(int t, int &r, int &c)
+{
+    int q = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (q * (q + 1) / 2 > t) --q;
+    while ((q + 1) * (q + 2) / 2 <= t) ++q;
+    r = q;
+    c = t - q * (q + 1) / 2;
+}
+
+template <typename T>
+__device__ __forceinline__ double ld(const void *p, int64_t i)
+{
+    return (double)((const T *)p)[i];
+}
+
+template <typename VT, typename XT, int MT>
+__global__ __launch_bounds__(256) void rows_f64_kernel(SideArgs a, int K, double alpha,
+                                                       double rbar, HyperDev hyp, DrawSrc draws,
+                                                       const int32_t *list,
+                                                       const int32_t *list_count,
+                                                       int64_t max_rows, DevState *state)
+{
+    extern __shared__ double sm[];
+    __shared__ int s_flag;
+    __shared__ int s_idx[F64_CH];
+    const int tid = threadIdx.x;
+    const int nb = (K + 3) >> 2;
+    const int KS = nb * 4;
+    const int T = nb * (nb + 1) / 2;
+    double *P = sm;                   // K*K
+    double *bv = P + K * K;           // K
+    double *zv = bv + K;              // K
+    double *stage = zv + K;           // F64_CH * KS
+    double *rv = stage + F64_CH * KS; // F64_CH
+
+    int tr[MT], tc[MT];
+    bool tv[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        int t = tid + 256 * m;
+        tv[m] = t < T;
+        tri_decode(tv[m] ? t : 0, tr[m], tc[m]);
+    }
+    const XT *other = (const XT *)a.other;
+    XT *X = (XT *)a.X;
+    const uint32_t h = draws.tape_rows ? 0u : half_sweep_index(draws);
+
+    const int64_t count = list ? (int64_t)(*list_count) : max_rows;
+    for (int64_t item = blockIdx.x; item < count; item += gridDim.x) {
+        const int row = list ? list[item] : (a.order ? a.order[item] : (int)item);
+        const int64_t s0 = a.ptr[row], s1 = a.ptr[row + 1];
+
+        double acc[MT][16];
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[m][e] = 0.0;
+        double bacc = 0.0;
+
+        for (int64_t c0 = s0; c0 < s1; c0 += F64_CH) {
+            const int cnt = (int)min((int64_t)F64_CH, s1 - c0);
+            if (tid < F64_CH) {
+                s_idx[tid] = tid < cnt ? a.idx[c0 + tid] : 0;
+                rv[tid] = tid < cnt ? ld<VT>(a.val, c0 + tid) - rbar : 0.0;
+            }
+            __syncthreads();
+            for (int e = tid; e < F64_CH * KS; e += 256) {
+                int n = e / KS, f = e - n * KS;
+                stage[e] = (n < cnt && f < K) ? (double)other[(int64_t)s_idx[n] * K + f] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                if (!tv[m]) continue;
+                for (int n = 0; n < cnt; ++n) {
+                    const double *sr = stage + n * KS;
+                    double x0 = sr[4 * tr[m] + 0], x1 = sr[4 * tr[m] + 1];
+                    double x2 = sr[4 * tr[m] + 2], x3 = sr[4 * tr[m] + 3];
+                    double y0 = sr[4 * tc[m] + 0], y1 = sr[4 * tc[m] + 1];
+                    double y2 = sr[4 * tc[m] + 2], y3 = sr[4 * tc[m] + 3];
+                    double xs[4] = {x0, x1, x2, x3}, ys[4] = {y0, y1, y2, y3};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc[m][i * 4 + j] = fma(xs[i], ys[j], acc[m][i * 4 + j]);
+                }
+            }
+            if (tid < K)
+                for (int n = 0; n < cnt; ++n) bacc = fma(rv[n], stage[n * KS + tid], bacc);
+            __syncthreads();
+        }
+
+        // P = Lambda + alpha G (lower triangle), b = Lambda mu + alpha sum r' v
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (!tv[m]) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int r = 4 * tr[m] + i, c = 4 * tc[m] + j;
+                    if (r < K && c <= r) P[r * K + c] = hyp.Lambda[r * K + c] + alpha * acc[m][i * 4 + j];
+                }
+        }
+        if (tid < K) bv[tid] = hyp.Lmu[tid] + alpha * bacc;
+        if (draws.tape_rows) {
+            for (int i = tid; i < K; i += 256) zv[i] = draws.tape_rows[(int64_t)row * K + i];
+        } else {
+            for (int p = tid; 2 * p < K; p += 256) {
+                double z0, z1;
+                box_muller_f64(philox4x32_10(ctr4((uint32_t)p, (uint32_t)row, h, 0u), draws.seed), z0, z1);
+                zv[2 * p] = z0;
+                if (2 * p + 1 < K) zv[2 * p + 1] = z1;
+            }
+        }
+        if (tid == 0) s_flag = 0;
+        __syncthreads();
+
+        // right-looking Cholesky, lower triangle in place
+        for (int k = 0; k < K; ++k) {
+            if (tid == 0) {
+                double d = P[k * K + k];
+                if (!(d > 0.0) || !isfinite(d)) {
+                    s_flag = 1;
+                    d = 1.0;
+                }
+                P[k * K + k] = sqrt(d);
+            }
+            __syncthreads();
+            const double dk = P[k * K + k];
+            for (int i = k + 1 + tid; i < K; i += 256) P[i * K + k] /= dk;
+            __syncthreads();
+            const int mrem = K - k - 1;
+            for (int ii = tid >> 4; ii < mrem; ii += 16) {
+                const int i = k + 1 + ii;
+                const double lik = P[i * K + k];
+                for (int jj = tid & 15; jj <= ii; jj += 16) {
+                    const int j = k + 1 + jj;
+                    P[i * K + j] = fma(-lik, P[j * K + k], P[i * K + j]);
+                }
+            }
+            __syncthreads();
+        }
+        // y = L^{-1} b
+        for (int k = 0; k < K; ++k) {
+            const double yk = bv[k] / P[k * K + k];
+            __syncthreads();
+            for (int i = k + 1 + tid; i < K; i += 256) bv[i] = fma(-P[i * K + k], yk, bv[i]);
+            if (tid == 0) bv[k] = yk;
+            __syncthreads();
+        }
+        // w = y + z ; x = L^{-T} w
+        for (int i = tid; i < K; i += 256) bv[i] += zv[i];
+        __syncthreads();
+        for (int k = K - 1; k >= 0; --k) {
+            const double xk = bv[k] / P[k * K + k];
+            __syncthreads();
+            for (int i = tid; i < k; i += 256) bv[i] = fma(-P[k * K + i], xk, bv[i]);
+            if (tid == 0) bv[k] = xk;
+            __syncthreads();
+        }
+        for (int i = tid; i < K; i += 256) {
+            const double x = bv[i];
+            if (!isfinite(x)) s_flag = 1;
+            X[(int64_t)row * K + i] = (XT)x;
+            if (a.X_bf16) a.X_bf16[(int64_t)row * a.shadow_stride + i] = f32_to_bf16_rne((float)x);
+        }
+        if (a.X_bf16)
+            for (int i = K + tid; i < a.shadow_stride; i += 256)
+                a.X_bf16[(int64_t)row * a.shadow_stride + i] = 0;
+        __syncthreads();
+        if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
+        __syncthreads();
+    }
+}
+
+// Side statistics: per chunk of rows, sum_i x_i (K) and the lower triangle of
+// sum_i x_i x_i^T (K(K+1)/2, packed by rows), in FP64.
+template <typename XT, int MT>
+__global__ __launch_bounds__(256) void stats_kernel(const XT *X, int64_t n, int K, double *partials,
+                                                    int n_chunks)
+{
+    __shared__ double stage[32 * 132];
+    const int tid = threadIdx.x;
+    const int nb = (K + 3) >> 2;
+    const int KS = nb * 4;
+    const int T = nb * (nb + 1) / 2;
+    const int E = K + K * (K + 1) / 2;
+    const int64_t r0 = n * blockIdx.x / n_chunks, r1 = n * (blockIdx.x + 1) / n_chunks;
+    int tr[MT], tc[MT];
+    bool tv[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        int t = tid + 256 * m;
+        tv[m] = t < T;
+        tri_decode(tv[m] ? t : 0, tr[m], tc[m]);
+    }
+    double acc[MT][16];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[m][e] = 0.0;
+    double sacc = 0.0;
+    for (int64_t c0 = r0; c0 < r1; c0 += 32) {
+        const int cnt = (int)min((int64_t)32, r1 - c0);
+        for (int e = tid; e < 32 * KS; e += 256) {
+            int q = e / KS, f = e - q * KS;
+            stage[e] = (q < cnt && f < K) ? (double)X[(c0 + q) * K + f] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if (!tv[m]) continue;
+            for (int q = 0; q < cnt; ++q) {
+                const double *sr = stage + q * KS;
+                double xs[4] = {sr[4 * tr[m]], sr[4 * tr[m] + 1], sr[4 * tr[m] + 2], sr[4 * tr[m] + 3]};
+                double ys[4] = {sr[4 * tc[m]], sr[4 * tc[m] + 1], sr[4 * tc[m] + 2], sr[4 * tc[m] + 3]};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[m][i * 4 + j] = fma(xs[i], ys[j], acc[m][i * 4 + j]);
+            }
+        }
+        if (tid < K)
+            for (int q = 0; q < cnt; ++q) sacc += stage[q * KS + tid];
+        __syncthreads();
+    }
+    double *out = partials + (int64_t)blockIdx.x * E;
+    if (tid < K) out[tid] = sacc;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        if (!tv[m]) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int r = 4 * tr[m] + i, c = 4 * tc[m] + j;
+                if (r < K && c <= r) out[K + r * (r + 1) / 2 + c] = acc[m][i * 4 + j];
+            }
+    }
+}
+
+template <typename XT>
+__global__ void predict_kernel(const XT *U, const XT *V, int K, double rbar, int64_t n,
+                               const int32_t *rows, const int32_t *cols, double *out,
+                               double *accum, const DevState *state, int burnin)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const XT *u = U + (int64_t)rows[t] * K;
+    const XT *v = V + (int64_t)cols[t] * K;
+    double p = rbar;
+    for (int a = 0; a < K; ++a) p = fma((double)u[a], (double)v[a], p);
+    if (out) out[t] = p;
+    if (accum && state->sweep >= burnin) accum[t] += p;
+}
+
+__global__ void advance_kernel(DevState *s, int burnin)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (s->sweep >= burnin) s->pred_count += 1;
+        s->fallback_rows += s->fb_count[0] + s->fb_count[1];
+        s->sweep += 1;
+    }
+}
+
+// Deterministic sum of the rating values: block b adds a fixed strided subset
+// in a fixed order, then a fixed-shape tree inside the block.
+template <typename VT>
+__global__ void sum_values_kernel(const VT *v, int64_t n, double *partials)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += (double)v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void mean_from_sum_kernel(const double *accum, int64_t n, const DevState *state, double *out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t c = state->pred_count;
+    out[t] = c > 0 ? accum[t] / (double)c : 0.0;
+}
+
+__global__ void reset_fb_kernel(DevState *s, int side)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) s->fb_count[side] = 0;
+}
+
+__global__ void to_bf16_kernel(const float *X, int64_t n, int K, int stride, uint16_t *out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * stride) return;
+    int64_t r = t / stride;
+    int c = (int)(t - r * stride);
+    out[t] = c < K ? f32_to_bf16_rne(X[r * K + c]) : (uint16_t)0;
+}
+
+__global__ void f64_to_f32_kernel(const double *in, float *out, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (float)in[t];
+}
+
+__global__ void fill_zero_kernel(uint32_t *p, int64_t n_words)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_words) p[t] = 0u;
+}
+
+template <typename XT>
+__global__ void copy_f32_kernel(const XT *in, float *out, int64_t n)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (float)in[t];
+}
+
+inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+size_t rows_f64_lds_bytes(int K)
+{
+    const int KS = ((K + 3) >> 2) * 4;
+    return sizeof(double) * ((size_t)K * K + 2 * K + (size_t)F64_CH * KS + F64_CH);
+}
+
+hipError_t launch_rows_f64(const SideArgs &a, int K, double alpha, double rbar, HyperDev hyp,
+                           DrawSrc draws, const int32_t *list, const int32_t *list_count,
+                           int64_t max_rows, int x_is_f32, DevState *state, hipStream_t s)
+{
+    if (max_rows <= 0) return hipSuccess;
+    const size_t lds = rows_f64_lds_bytes(K);
+    const int nb = (K + 3) >> 2;
+    (void)0;
+    const bool big = nb * (nb + 1) / 2 > 256;
+    unsigned grid = list ? (unsigned)std::min<int64_t>(max_rows, 2048) : (unsigned)max_rows;
+#define BPMF_LAUNCH_F64(VT, XT, MT)                                                              \
+    do {                                                                                          \
+        auto kfn = rows_f64_kernel<VT, XT, MT>;                                                   \
+        hipLaunchKernelGGL(kfn, dim3(grid), dim3(256), lds, s, a, K, alpha, rbar, hyp, draws,     \
+                           list, list_count, max_rows, state);                                    \
+    } while (0)
+    if (a.val_is_f64) {
+        if (x_is_f32) {
+            if (big) BPMF_LAUNCH_F64(double, float, 3); else BPMF_LAUNCH_F64(double, float, 1);
+        } else {
+            if (big) BPMF_LAUNCH_F64(double, double, 3); else BPMF_LAUNCH_F64(double, double, 1);
+        }
+    } else {
+        if (x_is_f32) {
+            if (big) BPMF_LAUNCH_F64(float, float, 3); else BPMF_LAUNCH_F64(float, float, 1);
+        } else {
+            if (big) BPMF_LAUNCH_F64(float, double, 3); else BPMF_LAUNCH_F64(float, double, 1);
+        }
+    }
+#undef BPMF_LAUNCH_F64
+    return hipGetLastError();
+}
+
+hipError_t prepare_rows_f64(int K)
+{
+    const int lds = (int)rows_f64_lds_bytes(K);
+    const void *fns[] = {(const void *)rows_f64_kernel<double, double, 1>, (const void *)rows_f64_kernel<double, double, 3>,
+                         (const void *)rows_f64_kernel<double, float, 1>, (const void *)rows_f64_kernel<double, float, 3>,
+                         (const void *)rows_f64_kernel<float, double, 1>, (const void *)rows_f64_kernel<float, double, 3>,
+                         (const void *)rows_f64_kernel<float, float, 1>, (const void *)rows_f64_kernel<float, float, 3>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_sum_values(const void *vals, int is_f64, int64_t n, double *partials, int nblk, hipStream_t s)
+{
+    if (is_f64) hipLaunchKernelGGL(sum_values_kernel<double>, dim3(nblk), dim3(256), 0, s, (const double *)vals, n, partials);
+    else hipLaunchKernelGGL(sum_values_kernel<float>, dim3(nblk), dim3(256), 0, s, (const float *)vals, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean_from_sum(const double *accum, int64_t n, const DevState *state, double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mean_from_sum_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, accum, n, state, out);
+    return hipGetLastError();
+}
+
+int stats_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 255) / 256)); }
+
+hipError_t launch_stats(const void *X, int x_is_f64, int64_t n, int K, double *partials,
+                        int n_chunks, hipStream_t s)
+{
+    const int nb = (K + 3) >> 2;
+    const bool big = nb * (nb + 1) / 2 > 256;
+    if (x_is_f64) {
+        if (big) hipLaunchKernelGGL((stats_kernel<double, 3>), dim3(n_chunks), dim3(256), 0, s, (const double *)X, n, K, partials, n_chunks);
+        else hipLaunchKernelGGL((stats_kernel<double, 1>), dim3(n_chunks), dim3(256), 0, s, (const double *)X, n, K, partials, n_chunks);
+    } else {
+        if (big) hipLaunchKernelGGL((stats_kernel<float, 3>), dim3(n_chunks), dim3(256), 0, s, (const float *)X, n, K, partials, n_chunks);
+        else hipLaunchKernelGGL((stats_kernel<float, 1>), dim3(n_chunks), dim3(256), 0, s, (const float *)X, n, K, partials, n_chunks);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, double rbar, int64_t n,
+                          const int32_t *rows, const int32_t *cols, double *out, double *accum,
+                          const DevState *state, int burnin, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (x_is_f64)
+        hipLaunchKernelGGL(predict_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                           (const double *)U, (const double *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
+    else
+        hipLaunchKernelGGL(predict_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                           (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_burnin(DevState *state, int burnin, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, state, burnin);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_fallback(DevState *state, int side, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_fb_kernel, dim3(1), dim3(64), 0, s, state, side);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *X, int64_t n, int K, int stride, uint16_t *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n * stride, 256)), dim3(256), 0, s, X, n, K, stride, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double *in, float *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
+{
+    int64_t words = (int64_t)(bytes / 4);
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(words, 256)), dim3(256), 0, s, (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f32_from(const void *X, int x_is_f64, int64_t n, float *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (x_is_f64)
+        hipLaunchKernelGGL(copy_f32_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, (const double *)X, out, n);
+    else
+        hipLaunchKernelGGL(copy_f32_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, (const float *)X, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace bpmf

@@ -1,0 +1,112 @@
+// kernels_mixed.hip -- mixed-precision row update, one wavefront per row.
+//
+// Same conditional as the FP64 path (paper: Section 2 and Algorithm 1; the
+// Cholesky-instead-of-inverse choice of Section 3.1):
+//   P = Lambda + alpha G,  G = sum_{j in Omega_i} v_j v_j^T,
+//   b = Lambda mu + alpha sum_j (r_ij - rbar) v_j,  x_i = L^{-T}(L^{-1} b + z_i).
+//
+// gfx950 mapping (K padded to KP = 32 or 64 with an identity block):
+//  * gather: each lane fetches 16-byte pieces of 4 rated rows; BF16 mode reads
+//    the BF16 copy of the other side (row stride KP), FP32 mode the FP32 master;
+//  * Gram on v_mfma_f32_32x32x16_bf16 (BF16) or v_mfma_f32_32x32x2_f32 (FP32),
+//    lower 32x32 tiles only, FP32 accumulation;
+//  * FP32 Cholesky and solves with one matrix row per lane;
+//  * a row whose pivot is not finite or not above 64 K 2^-24 max_k P_kk is not
+//    written; it is appended to a list that the FP64 kernel recomputes.
+#include "common.hpp"
+#include "rng.hpp"
+#include "rowsolve.hpp"
+
+namespace bpmf {
+
+namespace {
+
+template <int KP, bool BF16>
+__global__ __launch_bounds__(64) void rows_mixed_kernel(SideArgs a, int K, float alpha, float rbar,
+                                                        HyperDev hyp, DrawSrc draws,
+                                                        int32_t *fb_list, DevState *state,
+                                                        int side)
+{
+    using S = RowShape<KP>;
+    __shared__ __attribute__((aligned(16))) float u[S::UNION];
+    __shared__ __attribute__((aligned(16))) float rv[64];
+    __shared__ __attribute__((aligned(16))) float colbuf[4 * KP];
+    __shared__ int sidx[16];
+
+    const int lane = threadIdx.x;
+    const int64_t slot = blockIdx.x;
+    const int row = a.order ? a.order[slot] : (int)slot;
+    const int64_t s0 = a.ptr[row], s1 = a.ptr[row + 1];
+    const float *vals = (const float *)a.val;
+
+    floatx16 acc[S::NTILE];
+#pragma unroll
+    for (int t = 0; t < S::NTILE; ++t)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
+    float bacc = 0.0f;
+
+    if constexpr (BF16)
+        gram_bf16<KP>(a.idx + s0, vals + s0, s1 - s0, a.other_bf16, a.shadow_stride, rbar,
+                      (char *)u, rv, acc, bacc);
+    else
+        gram_f32<KP>(a.idx + s0, vals + s0, s1 - s0, (const float *)a.other, K, rbar, u, rv,
+                     sidx, acc, bacc);
+
+    float *tri = u;
+    const float *Lf = hyp.Lambda_f;
+    store_precision<KP>(tri, acc, K, alpha, [=](int r, int c) { return Lf[r * K + c]; });
+    const int ri = lane % KP;
+    const float bb = (ri < K) ? fmaf(alpha, bacc, hyp.Lmu_f[ri]) : 0.0f;
+
+    float z;
+    if (draws.tape_rows) {
+        z = (ri < K) ? (float)draws.tape_rows[(int64_t)row * K + ri] : 0.0f;
+    } else {
+        const uint32_t h = half_sweep_index(draws);
+        if (lane < KP / 2) {
+            float z0, z1;
+            box_muller_f32(philox4x32_10(ctr4((uint32_t)lane, (uint32_t)row, h, 0u), draws.seed), z0, z1);
+            colbuf[2 * lane] = z0;
+            colbuf[2 * lane + 1] = z1;
+        }
+        __syncthreads();
+        z = (ri < K) ? colbuf[ri] : 0.0f;
+    }
+    __syncthreads();
+
+    bool fail;
+    const float x = chol_solve<KP>(tri, colbuf, K, bb, z, fail);
+    if (!fail) {
+        float *X = (float *)a.X;
+        if (lane < KP && ri < K) X[(int64_t)row * K + ri] = x;
+        if (a.X_bf16 && lane < KP)
+            a.X_bf16[(int64_t)row * a.shadow_stride + ri] = ri < K ? f32_to_bf16_rne(x) : (uint16_t)0;
+    } else if (lane == 0) {
+        const int pos = atomicAdd(&state->fb_count[side], 1);
+        fb_list[pos] = row;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double alpha, double rbar,
+                             HyperDev hyp, DrawSrc draws, int32_t *fb_list, DevState *state,
+                             hipStream_t s)
+{
+    if (a.n_rows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.n_rows), block(64);
+    const float fa = (float)alpha, fr = (float)rbar;
+    if (KP == 64) {
+        if (bf16) hipLaunchKernelGGL((rows_mixed_kernel<64, true>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side);
+        else hipLaunchKernelGGL((rows_mixed_kernel<64, false>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side);
+    } else if (KP == 32) {
+        if (bf16) hipLaunchKernelGGL((rows_mixed_kernel<32, true>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side);
+        else hipLaunchKernelGGL((rows_mixed_kernel<32, false>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bpmf

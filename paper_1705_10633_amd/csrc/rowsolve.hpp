@@ -1,0 +1,259 @@
+// rowsolve.hpp -- wavefront-level building blocks of the mixed-precision row
+// update (one 64-lane wavefront per row, KP = 32 or 64 padded latent size):
+//   gram_bf16 / gram_f32 : G = sum_j v_j v_j^T (lower 32x32 tiles) and
+//                          sum_j (r_j - rbar) v_j on the matrix cores;
+//   store_precision      : P = Lambda + alpha G into a packed lower triangle
+//                          (padding rows/columns get the identity);
+//   chol_solve           : x = L^{-T}(L^{-1} b + z) with L L^T = P, FP32,
+//                          one matrix row per lane.
+// The paper's row conditional (Section 2, Algorithm 1) and the choice of a
+// Cholesky factorisation over an inverse (Section 3.1).
+#pragma once
+#include "common.hpp"
+
+namespace bpmf {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int KP>
+struct RowShape {
+    static constexpr int TRI = KP * (KP + 1) / 2 + KP;   // packed lower triangle + pad
+    static constexpr int FB = KP / 8;                    // 8-feature blocks per row
+    static constexpr int RG = 64 / FB;                   // 4-row groups per chunk
+    static constexpr int CH = 4 * RG;                    // BF16 chunk rows
+    static constexpr int SB = CH * 2 + 16;               // bytes per staged feature row
+    static constexpr int STAGE_BF16 = KP * SB / 4;       // floats
+    static constexpr int CHF = 16;                       // FP32 chunk rows
+    static constexpr int KSF = KP + 4;                   // FP32 stage row stride (floats)
+    static constexpr int STAGE_F32 = CHF * KSF;
+    static constexpr int U0 = TRI > STAGE_BF16 ? TRI : STAGE_BF16;
+    static constexpr int UNION = U0 > STAGE_F32 ? U0 : STAGE_F32;
+    static constexpr int NTILE = KP == 64 ? 3 : 1;
+};
+
+__device__ __forceinline__ float readlane_f(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// BF16 gathers: rows `idx[0..nnz)` of `src` (BF16, row stride `stride`,
+// 16-byte aligned rows) with ratings `vals` (FP32).  The chunk is staged
+// feature-major so each lane's matrix-core operand (8 consecutive nnz of one
+// feature) is one 16-byte LDS read.
+template <int KP>
+__device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals, int64_t nnz,
+                                          const uint16_t *src, int stride, float rbar, char *stage,
+                                          float *rv, floatx16 *acc, float &bacc)
+{
+    using S = RowShape<KP>;
+    const int lane = threadIdx.x & 63;
+    const int fb = lane % S::FB, rg = lane / S::FB;
+    for (int64_t c0 = 0; c0 < nnz; c0 += S::CH) {
+        const int cnt = (int)min((int64_t)S::CH, nnz - c0);
+        uint4 d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int n = rg * 4 + q;
+            if (n < cnt) {
+                const int64_t j = idx[c0 + n];
+                d[q] = *(const uint4 *)(src + j * stride + fb * 8);
+            } else {
+                d[q] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+        if (fb == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n = rg * 4 + q;
+                rv[n] = n < cnt ? vals[c0 + n] - rbar : 0.0f;
+            }
+        }
+        const uint32_t w0[4] = {d[0].x, d[0].y, d[0].z, d[0].w};
+        const uint32_t w1[4] = {d[1].x, d[1].y, d[1].z, d[1].w};
+        const uint32_t w2[4] = {d[2].x, d[2].y, d[2].z, d[2].w};
+        const uint32_t w3[4] = {d[3].x, d[3].y, d[3].z, d[3].w};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int f = fb * 8 + 2 * w;
+            uint2 lo, hi;
+            lo.x = (w0[w] & 0xffffu) | (w1[w] << 16);
+            lo.y = (w2[w] & 0xffffu) | (w3[w] << 16);
+            hi.x = (w0[w] >> 16) | (w1[w] & 0xffff0000u);
+            hi.y = (w2[w] >> 16) | (w3[w] & 0xffff0000u);
+            *(uint2 *)(stage + f * S::SB + rg * 8) = lo;
+            *(uint2 *)(stage + (f + 1) * S::SB + rg * 8) = hi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < S::CH / 16; ++ks) {
+            const int off = (ks * 16 + (lane >> 5) * 8) * 2;
+            const bf16x8_t F0 = *(const bf16x8_t *)(stage + (lane & 31) * S::SB + off);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F0, F0, acc[0], 0, 0, 0);
+            if constexpr (KP == 64) {
+                const bf16x8_t F1 = *(const bf16x8_t *)(stage + (32 + (lane & 31)) * S::SB + off);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F0, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, acc[2], 0, 0, 0);
+            }
+        }
+        {
+            constexpr int SPLIT = 64 / KP;
+            constexpr int PER = S::CH / SPLIT;
+            const int f = lane % KP, part = lane / KP;
+            const uint16_t *sp = (const uint16_t *)(stage + f * S::SB) + part * PER;
+#pragma unroll 8
+            for (int n = 0; n < PER; ++n) bacc = fmaf(bf16_to_f32(sp[n]), rv[part * PER + n], bacc);
+        }
+        __syncthreads();
+    }
+    if constexpr (KP == 32) bacc += __shfl_xor(bacc, 32);
+}
+
+// FP32 gathers of rows `idx` of `src` (row stride K), Gram on FP32 matrix cores.
+template <int KP>
+__device__ __forceinline__ void gram_f32(const int32_t *idx, const float *vals, int64_t nnz,
+                                         const float *src, int K, float rbar, float *stage,
+                                         float *rv, int *sidx, floatx16 *acc, float &bacc)
+{
+    using S = RowShape<KP>;
+    const int lane = threadIdx.x & 63;
+    for (int64_t c0 = 0; c0 < nnz; c0 += S::CHF) {
+        const int cnt = (int)min((int64_t)S::CHF, nnz - c0);
+        if (lane < S::CHF) {
+            sidx[lane] = lane < cnt ? idx[c0 + lane] : 0;
+            rv[lane] = lane < cnt ? vals[c0 + lane] - rbar : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < S::CHF * KP / 64; ++t) {
+            const int e = lane + 64 * t;
+            const int n = e / KP, f = e % KP;
+            stage[n * S::KSF + f] = (n < cnt && f < K) ? src[(int64_t)sidx[n] * K + f] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < S::CHF / 2; ++ks) {
+            const float *sr = stage + (2 * ks + (lane >> 5)) * S::KSF;
+            const float A0 = sr[lane & 31];
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0, A0, acc[0], 0, 0, 0);
+            if constexpr (KP == 64) {
+                const float A1 = sr[32 + (lane & 31)];
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1, A0, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1, A1, acc[2], 0, 0, 0);
+            }
+        }
+        {
+            constexpr int SPLIT = 64 / KP;
+            constexpr int PER = S::CHF / SPLIT;
+            const int f = lane % KP, part = lane / KP;
+#pragma unroll
+            for (int n = 0; n < PER; ++n)
+                bacc = fmaf(stage[(part * PER + n) * S::KSF + f], rv[part * PER + n], bacc);
+        }
+        __syncthreads();
+    }
+    if constexpr (KP == 32) bacc += __shfl_xor(bacc, 32);
+}
+
+// P = Lambda + alpha G into the packed lower triangle `tri` (row r starts at
+// r(r+1)/2).  lam(r, c) returns Lambda_rc for r, c < K.
+template <int KP, typename LamFn>
+__device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc, int K, float alpha,
+                                                LamFn lam)
+{
+    using S = RowShape<KP>;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t < S::NTILE; ++t) {
+        const int ta = (t == 0) ? 0 : 1, tb = (t == 2) ? 1 : 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 32 * ta + 8 * j + 4 * (lane >> 5) + i;
+                const int c = 32 * tb + (lane & 31);
+                if (c <= r) {
+                    float v;
+                    if (r < K && c < K) v = fmaf(alpha, acc[t][4 * j + i], lam(r, c));
+                    else v = (r == c) ? 1.0f : 0.0f;
+                    tri[r * (r + 1) / 2 + c] = v;
+                }
+            }
+    }
+}
+
+// Factor P (packed in `tri`) and return x = L^{-T}(L^{-1} b + z) on lane
+// ri = lane % KP, where lane ri holds b_ri and z_ri.  `fail` is set (uniformly
+// across the wave) when a pivot is not finite or not above
+// 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with L; `aux` holds 4 KP floats.
+//
+// Lane ri keeps row ri of P in registers.  Step k scales column k by
+// 1/sqrt(P_kk) (lane k thereby holds L_kk) and broadcasts it through LDS for
+// the rank-1 update of the trailing rows.  Entries right of the diagonal are
+// updated too but never read, and a lane whose solution component is final
+// keeps computing on values nobody reads, so the loops need no lane masks.
+template <int KP>
+__device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float bb, float z,
+                                            bool &fail)
+{
+    const int lane = threadIdx.x & 63;
+    const int ri = lane % KP;
+    float *colbuf = aux, *invbuf = aux + KP, *ybuf = aux + 2 * KP, *xbuf = aux + 3 * KP;
+    const int rbase = ri * (ri + 1) / 2;
+    float A[KP];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) A[c] = tri[rbase + c];
+    float dg = (ri < K) ? tri[rbase + ri] : 0.0f;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) dg = fmaxf(dg, __shfl_xor(dg, o));
+    const float tau = 64.0f * (float)K * 0x1.0p-24f * dg;
+
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        float pkk = readlane_f(A[k], k);
+        const bool bk = !(pkk > tau) || !(pkk < 3.0e38f);
+        bad = bad || bk;
+        pkk = bk ? 1.0f : pkk;
+        const float inv = __builtin_amdgcn_rsqf(pkk);
+        A[k] *= inv;
+        invbuf[k] = inv;
+        if (k + 1 < KP) {
+            if (lane < KP) colbuf[lane] = A[k];
+            __syncthreads();
+#pragma unroll
+            for (int j = k + 1; j < KP; ++j) A[j] = fmaf(-A[k], colbuf[j], A[j]);
+            __syncthreads();
+        }
+    }
+    fail = bad;
+    const float invd = invbuf[ri];
+    // y = L^{-1} b: y_k is taken from lane k before later steps overwrite it
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const float yk = readlane_f(bb * invd, k);
+        ybuf[k] = yk;
+        bb = fmaf(-A[k], yk, bb);
+    }
+    __syncthreads();
+    float w = ybuf[ri] + z;
+    // x = L^{-T} w with the rows of L written back to LDS
+    if (lane < KP) {
+#pragma unroll
+        for (int c = 0; c < KP; ++c)
+            if (c <= ri) tri[rbase + c] = A[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = KP - 1; k >= 0; --k) {
+        const float xk = readlane_f(w * invd, k);
+        xbuf[k] = xk;
+        w = fmaf(-tri[k * (k + 1) / 2 + ri], xk, w);
+    }
+    __syncthreads();
+    const float x = xbuf[ri];
+    __syncthreads();
+    return x;
+}
+
+}  // namespace bpmf

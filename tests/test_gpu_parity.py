@@ -1,0 +1,199 @@
+"""GPU path (libbpmf.so through its C ABI) against the FP64 CPU oracle.
+
+FP64 mode: given identical draws the GPU and the oracle compute the same
+samples up to rounding order; the bar is a per-row relative difference of
+1e-10 (row norm, floored at 1e-3 of the matrix RMS).
+Mixed modes: one sweep from an identical state and draw tape; the per-row
+error statistics are bounded by figures derived from the arithmetic (see the
+tolerance comments) and printed.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1705_10633_amd import synth
+
+from .gpu_common import make_sampler, row_rel_err, tape_for
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def with_empty(prob, rows, cols):
+    """The same problem with every rating of the given rows and columns removed."""
+    R = prob.R
+    r = np.repeat(np.arange(R.M), R.row_counts())
+    c = R.col_idx.astype(np.int64)
+    keep = ~np.isin(r, rows) & ~np.isin(c, cols)
+    p = synth.Problem(**{**prob.__dict__})
+    p.R = synth.from_coo(R.M, R.N, r[keep], c[keep], R.row_val[keep])
+    return p
+
+
+def _run_gpu(prob, tape, n_sweeps, precision="fp64", **kw):
+    s = make_sampler(prob, precision=precision, **kw)
+    s.sweep(n_sweeps, tape=_dev(tape) if tape is not None else None)
+    import torch
+    torch.cuda.synchronize()
+    return s
+
+
+@pytest.mark.parametrize("n_sweeps", [1, 20])
+def test_fp64_tape_parity_uniform_planted(n_sweeps):
+    prob = synth.uniform_planted(n_sweeps=n_sweeps, burnin=0)
+    tape = tape_for(prob, n_sweeps)
+    ref = O.gibbs(prob, tape, nthreads=8, want_hyper=True)
+    s = _run_gpu(prob, tape, n_sweeps)
+    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    print(f"sweeps={n_sweeps} max row err U {eu.max():.3e} V {ev.max():.3e}")
+    assert eu.max() <= FP64_TOL and ev.max() <= FP64_TOL
+    h = s.hyper()
+    for k in ("Lambda_U", "mu_U", "Lambda_V", "mu_V"):
+        a, b = h[k], ref["hyper"][k]
+        assert np.max(np.abs(a - b)) <= FP64_TOL * max(1.0, np.max(np.abs(b))), k
+    mean, cnt = s.test_predictions()
+    assert cnt == ref["pred_cnt"] == n_sweeps
+    np.testing.assert_allclose(mean.cpu().numpy(), ref["pred_mean"], rtol=FP64_TOL, atol=FP64_TOL)
+    p = s.predict(prob.test_rows[:50], prob.test_cols[:50]).cpu().numpy()
+    np.testing.assert_allclose(p, O.predict(ref["U"], ref["V"], prob.test_rows[:50], prob.test_cols[:50],
+                                            prob.mean_rating), rtol=FP64_TOL, atol=FP64_TOL)
+
+
+def test_fp64_device_generator_parity():
+    """Device Philox draws vs the oracle's own Philox / Box-Muller / Marsaglia-Tsang tape."""
+    prob = synth.uniform_planted(M=300, N=200, nnz=6000, seed=11, n_sweeps=3, burnin=0)
+    seed = 0x1234ABCD5678
+    tape = O.philox_tape(seed, 0, 3, prob.M, prob.N, prob.K, prob.nu0)
+    ref = O.gibbs(prob, tape, nthreads=8)
+    s = _run_gpu(prob, None, 3, seed=seed)
+    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    print(f"philox max row err U {eu.max():.3e} V {ev.max():.3e}")
+    assert eu.max() <= FP64_TOL and ev.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("K,M,N,nnz", [(1, 40, 30, 300), (3, 50, 41, 200), (33, 70, 65, 900),
+                                       (70, 60, 50, 1500), (100, 40, 35, 800), (128, 30, 28, 700)])
+def test_fp64_shapes_and_empty_rows(K, M, N, nnz):
+    """Odd K (padding of the 4x4 tiles), K up to 128, rows and columns with no ratings."""
+    prob = with_empty(synth.uniform_planted(M=M, N=N, K=K, nnz=nnz, seed=K + M, n_sweeps=2, burnin=0),
+                      rows=[0, M // 2], cols=[1, N - 1])
+    assert np.sum(prob.R.row_counts() == 0) >= 2 and np.sum(prob.R.col_counts() == 0) >= 2
+    tape = tape_for(prob, 2, seed=K)
+    ref = O.gibbs(prob, tape, nthreads=8)
+    s = _run_gpu(prob, tape, 2)
+    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    print(f"K={K} max row err U {eu.max():.3e} V {ev.max():.3e}")
+    assert eu.max() <= FP64_TOL and ev.max() <= FP64_TOL
+
+
+def _one_sweep_from_f32_state(prob, precision, tape):
+    """GPU mixed sweep and the FP64 oracle from the same FP32-rounded start."""
+    p32 = synth.Problem(**{**prob.__dict__})
+    p32.U0 = prob.U0.astype(np.float32).astype(np.float64)
+    p32.V0 = prob.V0.astype(np.float32).astype(np.float64)
+    ref = O.gibbs(p32, tape, n_sweeps=1, nthreads=8, want_hyper=True)
+    s = _run_gpu(p32, tape, 1, precision=precision)
+    return s, ref
+
+
+# Tolerances for one mixed sweep (median, max of the per-row relative error of
+# the users' half; the movies' half also carries the users' error).
+#  FP32: Gram, Cholesky and solves in FP32 with inputs exact in FP32: unit
+#        roundoff 6e-8 times K-sized sums and cond(P) (< ~1e3 here) -> 1e-5 / 1e-3.
+#  BF16: gathered rows rounded to 8 bits (relative 2^-9 = 2e-3); the Gram and
+#        rhs errors are amplified by cond(P) -> median 1e-2, max 1e-1.
+MIXED_TOL = {"fp32": (1e-5, 1e-3), "bf16": (1e-2, 1e-1)}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("K", [10, 32, 64])
+def test_mixed_one_sweep_error(precision, K):
+    prob = synth.uniform_planted(M=600, N=300, K=K, nnz=30000, seed=K, n_sweeps=1, burnin=0)
+    tape = tape_for(prob, 1, seed=K + 1)
+    s, ref = _one_sweep_from_f32_state(prob, precision, tape)
+    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    med, mx = MIXED_TOL[precision]
+    print(f"{precision} K={K}: U median {np.median(eu):.2e} p99 {np.quantile(eu, .99):.2e} max {eu.max():.2e}; "
+          f"V median {np.median(ev):.2e} max {ev.max():.2e}; fallback {s.info()['fallback_rows']}")
+    assert np.median(eu) <= med and eu.max() <= mx
+    assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx
+
+
+def test_fp32_pivot_failure_falls_back_to_fp64():
+    """Huge alpha with single-rating rows makes the FP32 pivots after the first
+    one fall under 64 K 2^-24 max P_kk; those rows are recomputed in FP64 from
+    the FP32 factors and then agree with the FP64 oracle to FP64 accuracy."""
+    M, N, K = 200, 150, 16
+    rng = np.random.default_rng(5)
+    rows = np.arange(M)
+    cols = rng.integers(0, N, M)
+    vals = rng.standard_normal(M)
+    R = synth.from_coo(M, N, rows, cols, vals)
+    prob = synth.Problem("single", R, K, 1e7, np.zeros(K), 2.0, float(K), np.eye(K), 1, 0,
+                         (0.1 * rng.standard_normal((M, K))).astype(np.float32).astype(np.float64),
+                         (0.1 * rng.standard_normal((N, K))).astype(np.float32).astype(np.float64),
+                         np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), 0, 0.0)
+    tape = tape_for(prob, 1, seed=3)
+    ref = O.gibbs(prob, tape, n_sweeps=1, nthreads=8)
+    s = make_sampler(prob, precision="fp32", with_test=False)
+    s.sweep(1, tape=_dev(tape))
+    info = s.info()
+    assert info["fallback_rows"] >= M  # every user row has one rating
+    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    print(f"fallback rows {info['fallback_rows']} max U err {eu.max():.2e}")
+    # FP64 arithmetic on FP32-stored inputs; the output is stored in FP32
+    assert eu.max() <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_graph_replay_equals_eager(precision):
+    prob = synth.uniform_planted(M=400, N=250, K=16, nnz=8000, seed=3, n_sweeps=3, burnin=1)
+    a = make_sampler(prob, precision=precision, seed=99, use_graph=False)
+    b = make_sampler(prob, precision=precision, seed=99, use_graph=True)
+    for _ in range(3):  # separate calls, with host synchronisation between replays
+        a.sweep(1)
+        b.sweep(1)
+        import torch
+        torch.cuda.synchronize()
+        assert torch.equal(a.U, b.U) and torch.equal(a.V, b.V)
+    ma, ca = a.test_predictions()
+    mb, cb = b.test_predictions()
+    assert ca == cb == 2
+    assert torch.equal(ma, mb)
+
+
+def test_state_save_restore_is_bitwise():
+    import torch
+    prob = synth.uniform_planted(M=300, N=200, K=12, nnz=5000, seed=4, n_sweeps=4, burnin=1)
+    s = make_sampler(prob, precision="bf16", seed=5)
+    s.sweep(2)
+    blob = s.save_state()
+    s.sweep(2)
+    U1, V1 = s.U.clone(), s.V.clone()
+    m1, c1 = s.test_predictions()
+    s.restore_state(blob)
+    s.sweep(2)
+    m2, c2 = s.test_predictions()
+    assert torch.equal(U1, s.U) and torch.equal(V1, s.V) and c1 == c2 and torch.equal(m1, m2)
+
+
+def test_fp64_is_deterministic():
+    import torch
+    prob = synth.uniform_planted(M=300, N=200, K=8, nnz=5000, seed=6, n_sweeps=2, burnin=0)
+    a = make_sampler(prob, seed=1)
+    b = make_sampler(prob, seed=1)
+    a.sweep(2)
+    b.sweep(2)
+    assert torch.equal(a.U, b.U) and torch.equal(a.V, b.V)
