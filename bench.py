@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark of the BPMF Gibbs sampler on one MI355X.
+
+Metric: Gibbs rows sampled per second at K = 64 (users + movies per sweep,
+whole sweeps including the hyper-parameter steps and the test predictions),
+next to the plain FP64 one-workgroup-per-row path on the same data, plus the
+p50 / p99 latency of batched fold-in serving.
+
+Workload (one step = one Gibbs sweep): the MovieLens-20M-shaped synthetic
+matrix, 138,493 x 26,744 with 20,000,000 ratings (log-normal row counts,
+half-star ratings from a planted rank-64 model), K = 64, BF16 gathers and
+Gram on matrix cores with FP32 accumulation, FP32 Cholesky, FP64 hyper step,
+device Philox draws, whole sweep replayed from a HIP graph.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Progress goes to stderr; one JSON line goes to stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X = {"hbm_GBs": 8000.0, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0, "fp64_TFLOPs": 78.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rows_kernel_flops(row_counts, col_counts, K):
+    """Algorithmic work of the row-update kernel over one sweep (both halves).
+
+    VALU (FP32): Cholesky K^3/3, two triangular solves 2 K^2, forming P
+    K(K+1), right-hand side 2 nnz K.  Matrix cores (BF16): the symmetric Gram
+    nnz K(K+1).
+    """
+    rows = row_counts.size + col_counts.size
+    nnz = int(row_counts.sum() + col_counts.sum())
+    valu = rows * (K ** 3 / 3.0 + 2.0 * K * K + K * (K + 1)) + 2.0 * nnz * K
+    mfma = float(nnz) * K * (K + 1)
+    return valu, mfma, rows, nnz
+
+
+def time_sweeps(sampler, steps, warmup):
+    import torch
+    sampler.sweep(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    sampler.sweep(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / steps, wall / steps * 1e3
+
+
+def cpu_baseline(prob, frac=0.25, seed=0):
+    """The FP64 oracle on a random sample of the rows of both halves of one sweep."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(seed)
+    nth = os.cpu_count() or 1
+    R, K = prob.R, prob.K
+    Lam = np.eye(K) * 2.0
+    mu = np.zeros(K)
+    total_rows, total_t = 0, 0.0
+    for ptr, idx, val, other, n in ((R.row_ptr, R.col_idx, R.row_val, prob.V0, R.M),
+                                    (R.col_ptr, R.row_idx, R.col_val, prob.U0, R.N)):
+        pick = np.sort(rng.choice(n, size=max(1, int(frac * n)), replace=False))
+        cnt = ptr[pick + 1] - ptr[pick]
+        sp = np.zeros(pick.size + 1, np.int64)
+        np.cumsum(cnt, out=sp[1:])
+        sel = np.concatenate([np.arange(ptr[i], ptr[i + 1]) for i in pick]) if pick.size else np.zeros(0, np.int64)
+        Z = rng.standard_normal((pick.size, K))
+        t0 = time.perf_counter()
+        O.half_sweep(sp, idx[sel], val[sel], other, prob.alpha, prob.mean_rating, Lam, mu, Z, nthreads=nth)
+        total_t += time.perf_counter() - t0
+        total_rows += pick.size
+    return {"value": total_rows / total_t, "unit": "rows/s", "cores": nth, "kind": "oracle",
+            "sample": f"FP64 oracle row updates of a uniform {int(frac * 100)}% sample of the rows of both "
+                      f"halves of one sweep ({total_rows} rows, {total_t:.1f} s wall, {nth} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--only-timed", action="store_true",
+                    help="run only warm-up and timed sweeps (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        log("bench.py: the sampler and its kernels run on one GPU; multi-GPU sharding is not built")
+        sys.exit(2)
+
+    import torch
+    from paper_1705_10633_amd import synth
+    from paper_1705_10633_amd.sampler import DeviceRatings, Sampler
+
+    t0 = time.perf_counter()
+    prob = synth.movielens_like()
+    K = prob.K
+    log(f"[bench] workload generated in {time.perf_counter() - t0:.1f} s: M={prob.M} N={prob.N} "
+        f"nnz={prob.R.nnz} K={K} ({prob.note})")
+
+    R32 = DeviceRatings(prob.R, val_dtype="float32")
+    s = Sampler(R32, K, prob.U0.astype(np.float32), prob.V0.astype(np.float32), precision="bf16",
+                alpha=prob.alpha, beta0=prob.beta0, nu0=prob.nu0, mean_rating=prob.mean_rating,
+                seed=2024, burnin=0, test_rows=prob.test_rows, test_cols=prob.test_cols,
+                use_graph=True)
+    rows_per_sweep = prob.M + prob.N
+    ms_dev, ms_wall = time_sweeps(s, args.steps, args.warmup)
+    value = rows_per_sweep / (ms_wall * 1e-3)
+    log(f"[bench] bf16 graph sweeps: {ms_wall:.3f} ms/sweep wall ({ms_dev:.3f} ms by events) "
+        f"-> {value:.4g} rows/s")
+    if args.only_timed:
+        print(json.dumps({"metric": "Gibbs rows sampled/sec at K=64", "value": value, "ms_per_step": ms_wall}))
+        return
+
+    # per-kernel durations over the same number of sweeps, events on the launch stream
+    s.set_timing(True)
+    s.sweep(args.steps)
+    tm = s.timing(reset=True)
+    s.set_timing(False)
+    info = s.info()
+    for k, (ms, n) in tm.items():
+        log(f"[bench]   {k:15s} {ms / max(n, 1) * 1e3:9.1f} us/launch x {n}")
+    rc, cc = prob.R.row_counts(), prob.R.col_counts()
+    valu, mfma, _, nnz = rows_kernel_flops(rc, cc, K)
+    t_rows = (tm["rows_users"][0] + tm["rows_movies"][0]) / args.steps  # ms per sweep, both launches
+    launches = 2
+    avg_launch_ms = t_rows / launches
+    achieved = (valu / launches) / (avg_launch_ms * 1e-3) / 1e12
+    mfma_achieved = (mfma / launches) / (avg_launch_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": MI355X["fp32_TFLOPs"], "unit": "TFLOP/s",
+                "frac": achieved / MI355X["fp32_TFLOPs"], "traffic": None}
+    detail = {"kernel": "rows_mixed_kernel<64,bf16>", "avg_launch_us": avg_launch_ms * 1e3,
+              "valu_flop_per_sweep": valu, "mfma_bf16_flop_per_sweep": mfma,
+              "mfma_bf16_achieved_TFLOPs": mfma_achieved,
+              "mfma_bf16_frac": mfma_achieved / MI355X["bf16_TFLOPs"],
+              "per_kernel_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in tm.items()},
+              "fallback_rows": info["fallback_rows"]}
+
+    fp64 = None
+    if not args.no_fp64:
+        del s
+        torch.cuda.empty_cache()
+        R64 = DeviceRatings(prob.R, val_dtype="float64")
+        s64 = Sampler(R64, K, prob.U0, prob.V0, precision="fp64", alpha=prob.alpha, beta0=prob.beta0,
+                      nu0=prob.nu0, mean_rating=prob.mean_rating, seed=2024, burnin=0,
+                      test_rows=prob.test_rows, test_cols=prob.test_cols, use_graph=True)
+        ms64_dev, ms64 = time_sweeps(s64, args.fp64_steps, 1)
+        fp64 = {"value": rows_per_sweep / (ms64 * 1e-3), "unit": "rows/s", "ms_per_step": ms64,
+                "path": "plain FP64, one 256-thread workgroup per row"}
+        log(f"[bench] fp64 plain sweeps: {ms64:.2f} ms/sweep -> {fp64['value']:.4g} rows/s "
+            f"(bf16 path is {value / fp64['value']:.1f}x)")
+        del s64, R64
+        torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serving:
+        try:
+            from paper_1705_10633_amd import serving as srv
+            serving = srv.bench_foldin(seconds=args.serve_seconds, log=log)
+        except (ImportError, AttributeError) as e:
+            log(f"[bench] serving skipped: {e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob)
+        log(f"[bench] cpu baseline: {cpu['value']:.4g} rows/s ({cpu['sample']})")
+
+    out = {
+        "metric": "Gibbs rows sampled/sec at K=64 (vs plain FP64 path) + p50/p99 fold-in latency",
+        "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "MovieLens-20M-shaped synthetic: 138,493 x 26,744, 20M ratings, K=64, "
+                               "BF16 gathers/Gram + FP32 Cholesky + FP64 hyper step, HIP-graph sweep",
+                   "M": prob.M, "N": prob.N, "nnz": prob.R.nnz, "K": K,
+                   "rows_per_step": rows_per_sweep, "n_test": int(prob.test_rows.size)},
+        "roofline": roofline,
+        "roofline_detail": detail,
+        "cpu_baseline": cpu,
+        "fp64_plain": fp64,
+        "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
+        "serving": serving,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

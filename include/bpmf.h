@@ -181,6 +181,21 @@ bpmf_status bpmf_state_size(bpmf_ctx *ctx, size_t *bytes);
 bpmf_status bpmf_state_save(bpmf_ctx *ctx, void *h_buf, size_t bytes, void *stream);
 bpmf_status bpmf_state_restore(bpmf_ctx *ctx, const void *h_buf, size_t bytes, void *stream);
 
+/* Per-kernel timing.  While enabled, sweeps run eagerly (no graph replay) and
+ * every launch is bracketed by HIP events recorded on the launch stream;
+ * bpmf_get_timing synchronises, resolves the pending events and returns the
+ * accumulated milliseconds and launch counts per kernel class:
+ * [0] side statistics, [1] hyper-parameter step, [2] users' row update,
+ * [3] movies' row update, [4] FP64 recompute of flagged rows,
+ * [5] predictions, [6] sweep counter. */
+#define BPMF_TIMING_CLASSES 7
+typedef struct {
+    double ms[BPMF_TIMING_CLASSES];
+    int64_t launches[BPMF_TIMING_CLASSES];
+} bpmf_timing;
+bpmf_status bpmf_set_timing(bpmf_ctx *ctx, int32_t enable);
+bpmf_status bpmf_get_timing(bpmf_ctx *ctx, bpmf_timing *out, int32_t reset);
+
 /* Releases the context (host objects and graphs only). NULL is ignored. */
 bpmf_status bpmf_destroy(bpmf_ctx *ctx);
 

@@ -46,6 +46,13 @@ class FoldinModel(C.Structure):
                 ("d_V", P), ("d_Lambda", P), ("d_mu", P)]
 
 
+TIMING_CLASSES = ("stats", "hyper", "rows_users", "rows_movies", "fp64_recompute", "predict", "counter")
+
+
+class Timing(C.Structure):
+    _fields_ = [("ms", F64 * 7), ("launches", I64 * 7)]
+
+
 class BpmfError(RuntimeError):
     def __init__(self, status, what, msg):
         super().__init__(f"{what}: {msg} (status {status})")
@@ -67,6 +74,8 @@ EXPORTS = {
     "bpmf_state_save": [P, P, SZ, P],
     "bpmf_state_restore": [P, P, SZ, P],
     "bpmf_destroy": [P],
+    "bpmf_set_timing": [P, I32],
+    "bpmf_get_timing": [P, P, I32],
     "bpmf_foldin_workspace_size": [P, I64, P],
     "bpmf_foldin": [P, I64, P, P, P, P, P, I64, P, P, SZ, P],
     "bpmf_status_string": [I32],

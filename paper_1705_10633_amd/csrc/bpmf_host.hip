@@ -64,7 +64,7 @@ struct WsLayout {
 };
 
 struct Offsets {
-    size_t state, partials[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], mu0, w0inv,
+    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], mu0, w0inv,
         order[2], fblist[2], shadow[2], valsf[2], accum, reduce;
     size_t total;
 };
@@ -85,6 +85,7 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
     for (int s = 0; s < 2; ++s) {
         const int nc = stats_chunks(n[s]);
         o.partials[s] = w.add(sizeof(double) * (size_t)nc * (K + K * (K + 1) / 2));
+        o.sums[s] = w.add(sizeof(double) * (size_t)(K + K * (K + 1) / 2));
         o.scratch[s] = w.add(sizeof(double) * nw_scratch_doubles(K));
         o.lam[s] = w.add(sizeof(double) * K * K);
         o.mu[s] = w.add(sizeof(double) * K);
@@ -121,6 +122,12 @@ struct bpmf_ctx {
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
     bool broken = false;
+    // per-kernel timing
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+    double t_ms[BPMF_TIMING_CLASSES] = {0};
+    int64_t t_n[BPMF_TIMING_CLASSES] = {0};
     bool x_f64() const { return precision == BPMF_FP64; }
     template <class T> T *at(size_t o) const { return (T *)(ws + o); }
 };
@@ -391,6 +398,37 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
 
 }  // extern "C"
 
+static hipEvent_t take_event(bpmf_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch timing: time_begin records a start event (timing enabled only),
+// time_end records the stop event and queues the pair under a kernel class.
+static hipEvent_t time_begin(bpmf_ctx *c, hipStream_t s)
+{
+    if (!c->timing) return nullptr;
+    hipEvent_t a = take_event(c);
+    if (a) hipEventRecord(a, s);
+    return a;
+}
+
+static void time_end(bpmf_ctx *c, int cls, hipEvent_t a, hipStream_t s)
+{
+    if (!c->timing || !a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    hipEventRecord(b, s);
+    c->pending.push_back({cls, {a, b}});
+}
+
 // One half-sweep on stream s.
 static bpmf_status enqueue_half(bpmf_ctx *c, int side, const double *tape_block, hipStream_t s)
 {
@@ -408,10 +446,16 @@ static bpmf_status enqueue_half(bpmf_ctx *c, int side, const double *tape_block,
     d.sweep = &c->state->sweep;
     d.side = side;
 
+    hipEvent_t t0 = time_begin(c, s);
     HIP_OK(launch_stats(X, f64 ? 1 : 0, n, K, c->at<double>(c->off.partials[side]), c->n_chunks[side], s));
-    HIP_OK(launch_nw(c->at<double>(c->off.partials[side]), c->n_chunks[side], n, K, c->at<double>(c->off.mu0),
-                     c->beta0, c->nu0, c->at<double>(c->off.w0inv), d, c->at<double>(c->off.scratch[side]),
-                     c->hyp[side], K <= 64 ? 1 : 0, s));
+    HIP_OK(launch_stats_reduce(c->at<double>(c->off.partials[side]), c->n_chunks[side], K,
+                               c->at<double>(c->off.sums[side]), s));
+    time_end(c, 0, t0, s);
+    t0 = time_begin(c, s);
+    HIP_OK(launch_nw(c->at<double>(c->off.sums[side]), n, K, c->at<double>(c->off.mu0), c->beta0, c->nu0,
+                     c->at<double>(c->off.w0inv), d, c->at<double>(c->off.scratch[side]), c->hyp[side],
+                     K <= 64 ? 1 : 0, c->state, s));
+    time_end(c, 1, t0, s);
 
     SideArgs a;
     a.n_rows = n;
@@ -427,7 +471,9 @@ static bpmf_status enqueue_half(bpmf_ctx *c, int side, const double *tape_block,
         a.val_is_f64 = R.val_is_f64;
         a.other_bf16 = nullptr;
         a.X_bf16 = nullptr;
+        t0 = time_begin(c, s);
         HIP_OK(launch_rows_f64(a, K, c->alpha, c->rbar, c->hyp[side], d, nullptr, nullptr, n, 0, c->state, s));
+        time_end(c, 2 + side, t0, s);
         return BPMF_OK;
     }
     const bool bf16 = c->precision == BPMF_BF16 && mixed_kernel;
@@ -437,14 +483,20 @@ static bpmf_status enqueue_half(bpmf_ctx *c, int side, const double *tape_block,
     a.X_bf16 = bf16 ? c->at<uint16_t>(c->off.shadow[side]) : nullptr;
     if (!mixed_kernel) {
         // K > 64: FP64 arithmetic on FP32 storage
+        t0 = time_begin(c, s);
         HIP_OK(launch_rows_f64(a, K, c->alpha, c->rbar, c->hyp[side], d, nullptr, nullptr, n, 1, c->state, s));
+        time_end(c, 2 + side, t0, s);
         return BPMF_OK;
     }
     HIP_OK(launch_reset_fallback(c->state, side, s));
+    t0 = time_begin(c, s);
     HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d,
                              c->at<int32_t>(c->off.fblist[side]), c->state, s));
+    time_end(c, 2 + side, t0, s);
+    t0 = time_begin(c, s);
     HIP_OK(launch_rows_f64(a, K, c->alpha, c->rbar, c->hyp[side], d, c->at<int32_t>(c->off.fblist[side]),
                            &c->state->fb_count[side], n, 1, c->state, s));
+    time_end(c, 4, t0, s);
     return BPMF_OK;
 }
 
@@ -456,10 +508,15 @@ static bpmf_status enqueue_sweep(bpmf_ctx *c, const double *tape, hipStream_t s)
     if (st != BPMF_OK) return st;
     st = enqueue_half(c, 1, tape ? tape + hb + c->R.M * K : nullptr, s);
     if (st != BPMF_OK) return st;
-    if (c->n_test > 0)
+    if (c->n_test > 0) {
+        hipEvent_t t0 = time_begin(c, s);
         HIP_OK(launch_predict(c->dU, c->dV, c->x_f64() ? 1 : 0, K, c->rbar, c->n_test, c->test_rows,
                               c->test_cols, nullptr, c->at<double>(c->off.accum), c->state, c->burnin, s));
+        time_end(c, 5, t0, s);
+    }
+    hipEvent_t t1 = time_begin(c, s);
     HIP_OK(launch_advance_burnin(c->state, c->burnin, s));
+    time_end(c, 6, t1, s);
     return BPMF_OK;
 }
 
@@ -483,7 +540,7 @@ bpmf_status bpmf_sweep(bpmf_ctx *c, int32_t n_sweeps, const double *d_tape, int6
         }
         return BPMF_OK;
     }
-    if (!c->use_graph) {
+    if (!c->use_graph || c->timing) {
         for (int i = 0; i < n_sweeps; ++i) {
             bpmf_status st = enqueue_sweep(c, nullptr, s);
             if (st != BPMF_OK) { c->broken = true; return st; }
@@ -635,9 +692,46 @@ bpmf_status bpmf_state_restore(bpmf_ctx *c, const void *h_buf, size_t bytes, voi
     return state_copy(c, (char *)h_buf, false, (hipStream_t)stream);
 }
 
+bpmf_status bpmf_set_timing(bpmf_ctx *c, int32_t enable)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    c->timing = enable != 0;
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_get_timing(bpmf_ctx *c, bpmf_timing *out, int32_t reset)
+{
+    if (!c || c->broken) return fail(BPMF_E_STATE, "context is NULL or unusable");
+    if (!out) return fail(BPMF_E_INVALID, "NULL output");
+    for (auto &p : c->pending) {
+        HIP_OK(hipEventSynchronize(p.second.second));
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        c->t_ms[p.first] += ms;
+        c->t_n[p.first] += 1;
+        c->pool.push_back(p.second.first);
+        c->pool.push_back(p.second.second);
+    }
+    c->pending.clear();
+    for (int i = 0; i < BPMF_TIMING_CLASSES; ++i) {
+        out->ms[i] = c->t_ms[i];
+        out->launches[i] = c->t_n[i];
+        if (reset) {
+            c->t_ms[i] = 0.0;
+            c->t_n[i] = 0;
+        }
+    }
+    return BPMF_OK;
+}
+
 bpmf_status bpmf_destroy(bpmf_ctx *c)
 {
     if (!c) return BPMF_OK;
+    for (auto &p : c->pending) {
+        hipEventDestroy(p.second.first);
+        hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : c->pool) hipEventDestroy(e);
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->graph) hipGraphDestroy(c->graph);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);

@@ -77,9 +77,11 @@ hipError_t launch_stats(const void *X, int x_is_f64, int64_t n, int K, double *p
                         int n_chunks, hipStream_t s);
 int stats_chunks(int64_t n);
 size_t nw_scratch_doubles(int K);
-hipError_t launch_nw(const double *partials, int n_chunks, int64_t n, int K, const double *mu0,
-                     double beta0, double nu0, const double *W0inv, DrawSrc draws,
-                     double *scratch, HyperDev hyp, int use_lds, hipStream_t s);
+hipError_t launch_stats_reduce(const double *partials, int n_chunks, int K, double *sums,
+                               hipStream_t s);
+hipError_t launch_nw(const double *sums, int64_t n, int K, const double *mu0, double beta0,
+                     double nu0, const double *W0inv, DrawSrc draws, double *scratch,
+                     HyperDev hyp, int use_lds, DevState *state, hipStream_t s);
 hipError_t launch_rows_f64(const SideArgs &a, int K, double alpha, double rbar,
                            HyperDev hyp, DrawSrc draws, const int32_t *list,
                            const int32_t *list_count, int64_t max_rows, int x_is_f32,

@@ -262,19 +262,30 @@ __global__ __launch_bounds__(256) void stats_kernel(const XT *X, int64_t n, int 
     }
 }
 
+// 16 lanes per pair: coalesced reads of both factor rows, FP64 accumulation,
+// shuffle reduction inside the 16-lane group.
 template <typename XT>
-__global__ void predict_kernel(const XT *U, const XT *V, int K, double rbar, int64_t n,
-                               const int32_t *rows, const int32_t *cols, double *out,
-                               double *accum, const DevState *state, int burnin)
+__global__ __launch_bounds__(256) void predict_kernel(const XT *U, const XT *V, int K, double rbar,
+                                                      int64_t n, const int32_t *rows,
+                                                      const int32_t *cols, double *out,
+                                                      double *accum, const DevState *state,
+                                                      int burnin)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const XT *u = U + (int64_t)rows[t] * K;
-    const XT *v = V + (int64_t)cols[t] * K;
-    double p = rbar;
-    for (int a = 0; a < K; ++a) p = fma((double)u[a], (double)v[a], p);
-    if (out) out[t] = p;
-    if (accum && state->sweep >= burnin) accum[t] += p;
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int l = threadIdx.x & 15;
+    double p = 0.0;
+    if (t < n) {
+        const XT *u = U + (int64_t)rows[t] * K;
+        const XT *v = V + (int64_t)cols[t] * K;
+        for (int f = l; f < K; f += 16) p = fma((double)u[f], (double)v[f], p);
+    }
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) p += __shfl_xor(p, o, 16);
+    if (t < n && l == 0) {
+        p += rbar;
+        if (out) out[t] = p;
+        if (accum && state->sweep >= burnin) accum[t] += p;
+    }
 }
 
 __global__ void advance_kernel(DevState *s, int burnin)
@@ -438,10 +449,10 @@ hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, dou
 {
     if (n <= 0) return hipSuccess;
     if (x_is_f64)
-        hipLaunchKernelGGL(predict_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(predict_kernel<double>, dim3(grid_for(n * 16, 256)), dim3(256), 0, s,
                            (const double *)U, (const double *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
     else
-        hipLaunchKernelGGL(predict_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(predict_kernel<float>, dim3(grid_for(n * 16, 256)), dim3(256), 0, s,
                            (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
     return hipGetLastError();
 }

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(64) void foldin_kernel(int S, int K, int64_t N, flo
     using SH = RowShape<KP>;
     __shared__ __attribute__((aligned(16))) float u[SH::UNION];
     __shared__ __attribute__((aligned(16))) float rv[64];
-    __shared__ __attribute__((aligned(16))) float colbuf[4 * KP];
+    __shared__ __attribute__((aligned(16))) float colbuf[3 * KP];
     __shared__ int sidx[16];
     const int lane = threadIdx.x;
     const int64_t r = blockIdx.x / S;

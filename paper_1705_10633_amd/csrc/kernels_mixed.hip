@@ -22,7 +22,7 @@ namespace bpmf {
 namespace {
 
 template <int KP, bool BF16>
-__global__ __launch_bounds__(64) void rows_mixed_kernel(SideArgs a, int K, float alpha, float rbar,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void rows_mixed_kernel(SideArgs a, int K, float alpha, float rbar,
                                                         HyperDev hyp, DrawSrc draws,
                                                         int32_t *fb_list, DevState *state,
                                                         int side)
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(64) void rows_mixed_kernel(SideArgs a, int K, float
     using S = RowShape<KP>;
     __shared__ __attribute__((aligned(16))) float u[S::UNION];
     __shared__ __attribute__((aligned(16))) float rv[64];
-    __shared__ __attribute__((aligned(16))) float colbuf[4 * KP];
+    __shared__ __attribute__((aligned(16))) float colbuf[3 * KP];
     __shared__ int sidx[16];
 
     const int lane = threadIdx.x;

@@ -2,17 +2,23 @@
 // "sample hyper-parameters ... based on U / V"; Section 2: Normal-Wishart
 // hyperpriors on the shared Gaussian prior of the rows).
 //
-// One workgroup, FP64.  From the per-chunk sums of x_i and x_i x_i^T:
+// From the sums of x_i and x_i x_i^T over the n rows of the side, FP64:
 //   xbar = sum x / n,  S = sum x x^T - n xbar xbar^T
 //   beta* = beta0 + n, nu* = nu0 + n, mu* = (beta0 mu0 + n xbar) / beta*
-//   P = W0^{-1} + S + (beta0 n / beta*)(xbar - mu0)(xbar - mu0)^T
-//   W* = P^{-1} = L^{-T} L^{-1} with L L^T = P
-//   L_W = chol(W*);  A lower with A_kk = sqrt(chi2(nu* - k)), A_kl ~ N(0,1)
-//   Lambda = (L_W A)(L_W A)^T  (Bartlett decomposition)
-//   mu = mu* + chol(beta* Lambda)^{-T} z
-// and Lambda mu, plus FP32 copies for the mixed-precision row kernels.
-// The K x K work matrices live in LDS for K <= 64 and in a global scratch
-// buffer (L2-resident) above that.
+//   P = W0^{-1} + S + (beta0 n / beta*)(xbar - mu0)(xbar - mu0)^T,  W* = P^{-1}
+//   Lambda = (L_W A)(L_W A)^T with L_W = chol(W*) and the Bartlett factor A
+//   (A_kk = sqrt(chi2(nu* - k)), A_kl ~ N(0,1) below the diagonal)
+//   mu = mu* + chol(beta* Lambda)^{-T} z.
+// Two identities keep this to one factorisation and two triangular solves:
+//  * with P = R R^T, R upper triangular with positive diagonal (a Cholesky
+//    factorisation that starts from the last pivot), R^{-T} is lower
+//    triangular with positive diagonal and R^{-T} R^{-1} = W*, so it is
+//    chol(W*); T = L_W A is then the solution of R^T T = A;
+//  * T is lower triangular with positive diagonal and T T^T = Lambda, so
+//    chol(beta* Lambda) = sqrt(beta*) T and the mean draw solves
+//    T^T d = z / sqrt(beta*).
+// One workgroup; the K x K work matrices live in LDS for K <= 64 and in a
+// global scratch buffer (L2-resident) above that.
 #include <algorithm>
 
 #include "common.hpp"
@@ -24,67 +30,49 @@ namespace {
 
 constexpr int NW_THREADS = 256;
 
-// In-place right-looking Cholesky of the lower triangle of A (stride K).
-__device__ void block_cholesky(double *A, int K, int *flag)
+// sums[e] = sum over chunks of partials[c][e]: 8 threads per entry over fixed
+// chunk ranges, combined by a fixed xor tree.
+__global__ __launch_bounds__(256) void stats_reduce_kernel(const double *partials, int n_chunks,
+                                                           int E, double *sums)
 {
-    const int tid = threadIdx.x;
-    for (int k = 0; k < K; ++k) {
-        if (tid == 0) {
-            double d = A[k * K + k];
-            if (!(d > 0.0) || !isfinite(d)) {
-                *flag = 1;
-                d = 1.0;
-            }
-            A[k * K + k] = sqrt(d);
-        }
-        __syncthreads();
-        const double dk = A[k * K + k];
-        for (int i = k + 1 + tid; i < K; i += NW_THREADS) A[i * K + k] /= dk;
-        __syncthreads();
-        const int mrem = K - k - 1;
-        for (int ii = tid >> 4; ii < mrem; ii += NW_THREADS / 16) {
-            const int i = k + 1 + ii;
-            const double lik = A[i * K + k];
-            for (int jj = tid & 15; jj <= ii; jj += 16) {
-                const int j = k + 1 + jj;
-                A[i * K + j] = fma(-lik, A[j * K + k], A[i * K + j]);
-            }
-        }
-        __syncthreads();
+    const int e = blockIdx.x * 32 + (threadIdx.x >> 3);
+    const int part = threadIdx.x & 7;
+    double s = 0.0;
+    if (e < E) {
+        const int c0 = n_chunks * part / 8, c1 = n_chunks * (part + 1) / 8;
+        for (int c = c0; c < c1; ++c) s += partials[(int64_t)c * E + e];
     }
+    s += __shfl_xor(s, 4, 8);
+    s += __shfl_xor(s, 2, 8);
+    s += __shfl_xor(s, 1, 8);
+    if (part == 0 && e < E) sums[e] = s;
 }
 
-__global__ __launch_bounds__(NW_THREADS) void nw_kernel(const double *partials, int n_chunks,
-                                                        int64_t n, int K, const double *mu0,
-                                                        double beta0, double nu0,
+template <bool USE_LDS>
+__global__ __launch_bounds__(NW_THREADS) void nw_kernel(const double *sums, int64_t n, int K,
+                                                        const double *mu0, double beta0, double nu0,
                                                         const double *W0inv, DrawSrc draws,
                                                         double *scratch, HyperDev hyp,
-                                                        int use_lds)
+                                                        DevState *state)
 {
     extern __shared__ double lds[];
     __shared__ int s_flag;
     const int tid = threadIdx.x;
     const int KK = K * K;
-    double *base = use_lds ? lds : scratch;
-    double *M1 = base;
-    double *M2 = M1 + KK;
-    double *xbar = M2 + KK;          // K
-    double *sums = xbar + K;         // K + K(K+1)/2
-    double *chi2 = sums + K + K * (K + 1) / 2;  // K
-    double *zb = chi2 + K;           // K(K-1)/2 (at least 1)
+    double *base = USE_LDS ? lds : scratch;
+    double *M1 = base;                    // P, then R (upper) / Lambda
+    double *M2 = M1 + KK;                 // T (lower)
+    double *xbar = M2 + KK;               // K
+    double *rd = xbar + K;                // K: diagonal of R
+    double *chi2 = rd + K;                // K
+    double *zb = chi2 + K;                // K(K-1)/2 (at least 1)
     double *zm = zb + max(1, K * (K - 1) / 2);  // K
-    double *dvec = zm + K;           // K
-    const int E = K + K * (K + 1) / 2;
+    double *dvec = zm + K;                // K
+    double *dout = dvec + K;              // K
     const double dn = (double)n;
     const double bstar = beta0 + dn, nstar = nu0 + dn;
 
     if (tid == 0) s_flag = 0;
-    // 1. fixed-order reduction of the chunk partials
-    for (int e = tid; e < E; e += NW_THREADS) {
-        double s = 0.0;
-        for (int c = 0; c < n_chunks; ++c) s += partials[(int64_t)c * E + e];
-        sums[e] = s;
-    }
     // draws
     if (draws.tape_nw) {
         for (int k = tid; k < K; k += NW_THREADS) chi2[k] = draws.tape_nw[k];
@@ -98,10 +86,9 @@ __global__ __launch_bounds__(NW_THREADS) void nw_kernel(const double *partials, 
             zb[q] = stream_normal_f64(draws.seed, h, 1u, (uint32_t)q);
         for (int q = tid; q < K; q += NW_THREADS) zm[q] = stream_normal_f64(draws.seed, h, 2u, (uint32_t)q);
     }
-    __syncthreads();
     for (int a = tid; a < K; a += NW_THREADS) xbar[a] = n > 0 ? sums[a] / dn : 0.0;
     __syncthreads();
-    // 2. P = W0^{-1} + S + coef (xbar - mu0)(xbar - mu0)^T, both triangles
+    // P = W0^{-1} + S + coef (xbar - mu0)(xbar - mu0)^T (both triangles)
     const double coef = beta0 * dn / bstar;
     for (int e = tid; e < KK; e += NW_THREADS) {
         const int a = e / K, c = e - a * K;
@@ -110,43 +97,40 @@ __global__ __launch_bounds__(NW_THREADS) void nw_kernel(const double *partials, 
         const double S = sxx - dn * xbar[a] * xbar[c];
         M1[e] = W0inv[e] + S + coef * (xbar[a] - mu0[a]) * (xbar[c] - mu0[c]);
     }
+    // P = R R^T from the last pivot up.  Step k reads column k of the
+    // remaining block from the lower positions (k, i), i < k, writes
+    // R_ik = P_ki / R_kk to the upper position (i, k) and updates the leading
+    // block's lower triangle; those positions are disjoint, so one barrier
+    // per step suffices.
+    for (int k = K - 1; k >= 0; --k) {
+        __syncthreads();
+        double akk = M1[k * K + k];
+        if (!(akk > 0.0) || !isfinite(akk)) {
+            if (tid == 0) s_flag = 1;
+            akk = 1.0;
+        }
+        const double rkk = sqrt(akk);
+        const double inv = 1.0 / rkk;
+        const double inv2 = 1.0 / akk;
+        if (tid == 0) rd[k] = rkk;
+        for (int i = tid; i < k; i += NW_THREADS) M1[i * K + k] = M1[k * K + i] * inv;
+        for (int ii = tid >> 4; ii < k; ii += NW_THREADS / 16) {
+            const double pki = M1[k * K + ii] * inv2;
+            for (int jj = tid & 15; jj <= ii; jj += 16) M1[ii * K + jj] = fma(-pki, M1[k * K + jj], M1[ii * K + jj]);
+        }
+    }
     __syncthreads();
-    // 3. L = chol(P)
-    block_cholesky(M1, K, &s_flag);
-    // 4. M2 = L^{-1}, column c by forward substitution (one thread per column)
+    // T: R^T T = A, one thread per column of A (both lower triangular)
     for (int c = tid; c < K; c += NW_THREADS) {
         for (int i = 0; i < c; ++i) M2[i * K + c] = 0.0;
-        M2[c * K + c] = 1.0 / M1[c * K + c];
-        for (int i = c + 1; i < K; ++i) {
-            double s = 0.0;
-            for (int m = c; m < i; ++m) s = fma(M1[i * K + m], M2[m * K + c], s);
-            M2[i * K + c] = -s / M1[i * K + i];
+        for (int i = c; i < K; ++i) {
+            double s = (i == c) ? sqrt(chi2[c]) : zb[i * (i - 1) / 2 + c];
+            for (int m = c; m < i; ++m) s = fma(-M1[m * K + i], M2[m * K + c], s);
+            M2[i * K + c] = s / rd[i];
         }
     }
     __syncthreads();
-    // 5. W* = L^{-T} L^{-1}
-    for (int e = tid; e < KK; e += NW_THREADS) {
-        const int a = e / K, c = e - a * K;
-        const int m0 = a > c ? a : c;
-        double s = 0.0;
-        for (int m = m0; m < K; ++m) s = fma(M2[m * K + a], M2[m * K + c], s);
-        M1[e] = s;
-    }
-    __syncthreads();
-    // 6. L_W = chol(W*)
-    block_cholesky(M1, K, &s_flag);
-    // 7. T = L_W A (lower)
-    for (int e = tid; e < KK; e += NW_THREADS) {
-        const int a = e / K, c = e - a * K;
-        double s = 0.0;
-        for (int m = c; m <= a; ++m) {
-            const double Amc = (m == c) ? sqrt(chi2[c]) : zb[m * (m - 1) / 2 + c];
-            s = fma(M1[a * K + m], Amc, s);
-        }
-        M2[e] = (c <= a) ? s : 0.0;
-    }
-    __syncthreads();
-    // 8. Lambda = T T^T
+    // Lambda = T T^T
     for (int e = tid; e < KK; e += NW_THREADS) {
         const int a = e / K, c = e - a * K;
         const int m1 = a < c ? a : c;
@@ -156,54 +140,64 @@ __global__ __launch_bounds__(NW_THREADS) void nw_kernel(const double *partials, 
         hyp.Lambda[e] = s;
         hyp.Lambda_f[e] = (float)s;
     }
-    __syncthreads();
-    // 9. chol(beta* Lambda) and mu = mu* + Lc^{-T} z
-    for (int e = tid; e < KK; e += NW_THREADS) M2[e] = bstar * M1[e];
-    __syncthreads();
-    block_cholesky(M2, K, &s_flag);
-    if (tid == 0) {
-        // backward substitution Lc^T d = z
-        for (int k = K - 1; k >= 0; --k) {
-            double s = zm[k];
-            for (int m = k + 1; m < K; ++m) s = fma(-M2[m * K + k], dvec[m], s);
-            dvec[k] = s / M2[k * K + k];
-        }
+    // mean: T^T d = z / sqrt(beta*), column-oriented backward substitution
+    const double isb = 1.0 / sqrt(bstar);
+    for (int a = tid; a < K; a += NW_THREADS) dvec[a] = zm[a] * isb;
+    for (int k = K - 1; k >= 0; --k) {
+        __syncthreads();
+        const double dk = dvec[k] / M2[k * K + k];
+        if (tid == 0) dout[k] = dk;
+        for (int i = tid; i < k; i += NW_THREADS) dvec[i] = fma(-M2[k * K + i], dk, dvec[i]);
     }
     __syncthreads();
     for (int a = tid; a < K; a += NW_THREADS) {
         const double mus = (beta0 * mu0[a] + dn * xbar[a]) / bstar;
-        hyp.mu[a] = mus + dvec[a];
+        hyp.mu[a] = mus + dout[a];
+        dvec[a] = mus + dout[a];
     }
     __syncthreads();
     for (int a = tid; a < K; a += NW_THREADS) {
         double s = 0.0;
-        for (int c = 0; c < K; ++c) s = fma(M1[a * K + c], hyp.mu[c], s);
+        for (int c = 0; c < K; ++c) s = fma(M1[a * K + c], dvec[c], s);
         hyp.Lmu[a] = s;
         hyp.Lmu_f[a] = (float)s;
     }
+    if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
 }
 
 }  // namespace
 
+size_t nw_scratch_doubles(int K)
+{
+    return (size_t)2 * K * K + 4 * (size_t)K + (size_t)std::max(1, K * (K - 1) / 2) + 3 * (size_t)K;
+}
+
 hipError_t prepare_nw(int K)
 {
     if (K > 64) return hipSuccess;
-    return hipFuncSetAttribute((const void *)nw_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    return hipFuncSetAttribute((const void *)nw_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(nw_scratch_doubles(K) * sizeof(double)));
 }
 
-size_t nw_scratch_doubles(int K)
+hipError_t launch_stats_reduce(const double *partials, int n_chunks, int K, double *sums, hipStream_t s)
 {
-    return (size_t)2 * K * K + K + K + K * (K + 1) / 2 + K + (size_t)std::max(1, K * (K - 1) / 2) + K + K;
+    const int E = K + K * (K + 1) / 2;
+    hipLaunchKernelGGL(stats_reduce_kernel, dim3((unsigned)((E + 31) / 32)), dim3(256), 0, s, partials,
+                       n_chunks, E, sums);
+    return hipGetLastError();
 }
 
-hipError_t launch_nw(const double *partials, int n_chunks, int64_t n, int K, const double *mu0,
-                     double beta0, double nu0, const double *W0inv, DrawSrc draws,
-                     double *scratch, HyperDev hyp, int use_lds, hipStream_t s)
+hipError_t launch_nw(const double *sums, int64_t n, int K, const double *mu0, double beta0, double nu0,
+                     const double *W0inv, DrawSrc draws, double *scratch, HyperDev hyp, int use_lds,
+                     DevState *state, hipStream_t s)
 {
     size_t lds = use_lds ? nw_scratch_doubles(K) * sizeof(double) : 0;
-    hipLaunchKernelGGL(nw_kernel, dim3(1), dim3(NW_THREADS), lds, s, partials, n_chunks, n, K,
-                       mu0, beta0, nu0, W0inv, draws, scratch, hyp, use_lds);
+    if (use_lds)
+        hipLaunchKernelGGL(nw_kernel<true>, dim3(1), dim3(NW_THREADS), lds, s, sums, n, K, mu0, beta0, nu0,
+                           W0inv, draws, scratch, hyp, state);
+    else
+        hipLaunchKernelGGL(nw_kernel<false>, dim3(1), dim3(NW_THREADS), 0, s, sums, n, K, mu0, beta0, nu0,
+                           W0inv, draws, scratch, hyp, state);
     return hipGetLastError();
 }
 

@@ -49,25 +49,48 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
     using S = RowShape<KP>;
     const int lane = threadIdx.x & 63;
     const int fb = lane % S::FB, rg = lane / S::FB;
-    for (int64_t c0 = 0; c0 < nnz; c0 += S::CH) {
-        const int cnt = (int)min((int64_t)S::CH, nnz - c0);
-        uint4 d[4];
+    // Software pipeline: the rows of chunk c+1 and the indices of chunk c+2
+    // are in flight while chunk c is staged and multiplied.
+    int jn[4], jnn[4];
+    float vn[4];
+    uint4 dn[4];
+    auto load_idx = [&](int64_t c0, int *j) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int n = rg * 4 + q;
-            if (n < cnt) {
-                const int64_t j = idx[c0 + n];
-                d[q] = *(const uint4 *)(src + j * stride + fb * 8);
-            } else {
-                d[q] = make_uint4(0u, 0u, 0u, 0u);
-            }
+            const int64_t n = c0 + rg * 4 + q;
+            j[q] = n < nnz ? idx[n] : -1;
+        }
+    };
+    auto load_rows = [&](int64_t c0, const int *j, uint4 *d, float *v) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            d[q] = j[q] >= 0 ? *(const uint4 *)(src + (int64_t)j[q] * stride + fb * 8)
+                             : make_uint4(0u, 0u, 0u, 0u);
+            const int64_t n = c0 + rg * 4 + q;
+            v[q] = (fb == 0 && n < nnz) ? vals[n] - rbar : 0.0f;
+        }
+    };
+    if (nnz > 0) {
+        load_idx(0, jn);
+        load_rows(0, jn, dn, vn);
+        load_idx(S::CH, jnn);
+    }
+    for (int64_t c0 = 0; c0 < nnz; c0 += S::CH) {
+        uint4 d[4];
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            d[q] = dn[q];
+            v[q] = vn[q];
+            jn[q] = jnn[q];
+        }
+        if (c0 + S::CH < nnz) {
+            load_rows(c0 + S::CH, jn, dn, vn);
+            load_idx(c0 + 2 * S::CH, jnn);
         }
         if (fb == 0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int n = rg * 4 + q;
-                rv[n] = n < cnt ? vals[c0 + n] - rbar : 0.0f;
-            }
+            for (int q = 0; q < 4; ++q) rv[rg * 4 + q] = v[q];
         }
         const uint32_t w0[4] = {d[0].x, d[0].y, d[0].z, d[0].w};
         const uint32_t w1[4] = {d[1].x, d[1].y, d[1].z, d[1].w};
@@ -185,20 +208,25 @@ __device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc,
 // Factor P (packed in `tri`) and return x = L^{-T}(L^{-1} b + z) on lane
 // ri = lane % KP, where lane ri holds b_ri and z_ri.  `fail` is set (uniformly
 // across the wave) when a pivot is not finite or not above
-// 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with L; `aux` holds 4 KP floats.
+// 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with L; `aux` holds 3 KP floats.
 //
-// Lane ri keeps row ri of P in registers.  Step k scales column k by
-// 1/sqrt(P_kk) (lane k thereby holds L_kk) and broadcasts it through LDS for
-// the rank-1 update of the trailing rows.  Entries right of the diagonal are
-// updated too but never read, and a lane whose solution component is final
-// keeps computing on values nobody reads, so the loops need no lane masks.
+// Lane ri keeps row ri of P in registers.  The factorisation runs in panels
+// of 8 columns: inside a panel, column k is scaled by 1/sqrt(P_kk) (lane k
+// thereby holds L_kk) and the later panel columns are updated with values
+// read across lanes with readlane; then every lane publishes its 8 panel
+// entries through LDS once and applies the rank-8 update to its trailing
+// columns.  Entries right of the diagonal are updated too but never read,
+// and a lane whose solution component is final keeps computing on values
+// nobody reads, so the loops need no lane masks.
 template <int KP>
 __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float bb, float z,
                                             bool &fail)
 {
+    constexpr int PW = 8;
     const int lane = threadIdx.x & 63;
     const int ri = lane % KP;
-    float *colbuf = aux, *invbuf = aux + KP, *ybuf = aux + 2 * KP, *xbuf = aux + 3 * KP;
+    float *invbuf = aux, *ybuf = aux + KP, *xbuf = aux + 2 * KP;
+    float *pbuf = tri;  // KP x 8 panel broadcast; P has been read into registers by then
     const int rbase = ri * (ri + 1) / 2;
     float A[KP];
 #pragma unroll
@@ -207,22 +235,44 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) dg = fmaxf(dg, __shfl_xor(dg, o));
     const float tau = 64.0f * (float)K * 0x1.0p-24f * dg;
+    __syncthreads();
 
     bool bad = false;
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-        float pkk = readlane_f(A[k], k);
-        const bool bk = !(pkk > tau) || !(pkk < 3.0e38f);
-        bad = bad || bk;
-        pkk = bk ? 1.0f : pkk;
-        const float inv = __builtin_amdgcn_rsqf(pkk);
-        A[k] *= inv;
-        invbuf[k] = inv;
-        if (k + 1 < KP) {
-            if (lane < KP) colbuf[lane] = A[k];
+    for (int c0 = 0; c0 < KP; c0 += PW) {
+#pragma unroll
+        for (int k = c0; k < c0 + PW; ++k) {
+            float pkk = readlane_f(A[k], k);
+            const bool bk = !(pkk > tau) || !(pkk < 3.0e38f);
+            bad = bad || bk;
+            pkk = bk ? 1.0f : pkk;
+            const float inv = __builtin_amdgcn_rsqf(pkk);
+            A[k] *= inv;
+            invbuf[k] = inv;
+#pragma unroll
+            for (int j = k + 1; j < c0 + PW; ++j) A[j] = fmaf(-A[k], readlane_f(A[k], j), A[j]);
+        }
+        if (c0 + PW < KP) {
+            if (lane < KP) {
+                *(float4 *)(pbuf + lane * PW) = make_float4(A[c0], A[c0 + 1], A[c0 + 2], A[c0 + 3]);
+                *(float4 *)(pbuf + lane * PW + 4) = make_float4(A[c0 + 4], A[c0 + 5], A[c0 + 6], A[c0 + 7]);
+            }
             __syncthreads();
 #pragma unroll
-            for (int j = k + 1; j < KP; ++j) A[j] = fmaf(-A[k], colbuf[j], A[j]);
+            for (int j = c0 + PW; j < KP; ++j) {
+                const float4 p0 = *(const float4 *)(pbuf + j * PW);
+                const float4 p1 = *(const float4 *)(pbuf + j * PW + 4);
+                float t = A[j];
+                t = fmaf(-A[c0 + 0], p0.x, t);
+                t = fmaf(-A[c0 + 1], p0.y, t);
+                t = fmaf(-A[c0 + 2], p0.z, t);
+                t = fmaf(-A[c0 + 3], p0.w, t);
+                t = fmaf(-A[c0 + 4], p1.x, t);
+                t = fmaf(-A[c0 + 5], p1.y, t);
+                t = fmaf(-A[c0 + 6], p1.z, t);
+                t = fmaf(-A[c0 + 7], p1.w, t);
+                A[j] = t;
+            }
             __syncthreads();
         }
     }
@@ -235,15 +285,14 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
         ybuf[k] = yk;
         bb = fmaf(-A[k], yk, bb);
     }
-    __syncthreads();
-    float w = ybuf[ri] + z;
-    // x = L^{-T} w with the rows of L written back to LDS
+    // rows of L back to LDS for the transposed solve
     if (lane < KP) {
 #pragma unroll
         for (int c = 0; c < KP; ++c)
             if (c <= ri) tri[rbase + c] = A[c];
     }
     __syncthreads();
+    float w = ybuf[ri] + z;
 #pragma unroll
     for (int k = KP - 1; k >= 0; --k) {
         const float xk = readlane_f(w * invd, k);

@@ -136,6 +136,16 @@ class Sampler:
         return {"sweeps_done": i.sweeps_done, "fallback_rows": i.fallback_rows,
                 "nonfinite_rows": i.nonfinite_rows, "mean_rating": i.mean_rating}
 
+    def set_timing(self, enable: bool):
+        """Bracket every launch with HIP events (sweeps then run without graph replay)."""
+        call("bpmf_set_timing", self.ctx, 1 if enable else 0)
+
+    def timing(self, reset: bool = True):
+        """Accumulated per-kernel-class milliseconds and launch counts."""
+        t = _lib.Timing()
+        call("bpmf_get_timing", self.ctx, C.byref(t), 1 if reset else 0)
+        return {name: (t.ms[i], t.launches[i]) for i, name in enumerate(_lib.TIMING_CLASSES)}
+
     def snapshot(self, V_slot, Lambda_slot, mu_slot, stream=None):
         call("bpmf_snapshot", self.ctx, _ptr(V_slot), _ptr(Lambda_slot), _ptr(mu_slot),
              _stream(self.torch, stream))
