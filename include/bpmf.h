@@ -236,6 +236,72 @@ bpmf_status bpmf_foldin(const bpmf_foldin_model *m, int64_t n_req, const int64_t
                         size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Fold-in serving engine: continuous batching on several streams             */
+/* ------------------------------------------------------------------------ */
+
+/* A server owns device buffers and pinned staging for n_streams batches in
+ * flight, sized so that all of them together stay within mem_budget_bytes,
+ * and a dispatcher thread.  Requests are queued by bpmf_server_submit (host
+ * arrays are copied; any thread).  Whenever a stream is free, the dispatcher
+ * takes queued requests in arrival order while the batch fits the stream's
+ * share of the budget, at most max_batch requests per batch and at most
+ * max_inflight requests on the GPU in total, uploads the batch, runs
+ * bpmf_foldin on it and downloads the predictions; batches on different
+ * streams overlap.  A request never waits for a batch to fill: a free stream
+ * takes what is queued.  Results are identical to serving the request alone
+ * (bpmf_foldin computes each request independently).
+ * The model arrays must stay alive and unchanged while the server exists. */
+typedef struct bpmf_server bpmf_server;
+
+typedef struct {
+    int64_t requests_done;
+    int64_t batches;
+    int64_t max_batch;        /* largest batch launched */
+    int64_t max_inflight;     /* most requests on the GPU at once */
+    int64_t max_batch_bytes;  /* largest batch footprint in device memory */
+    int64_t stream_capacity;  /* bytes available to one batch */
+} bpmf_server_stats;
+
+/* Errors: BPMF_E_INVALID (model, n_streams < 1, budget too small for one
+ * request of one rating and one query), BPMF_E_HIP, BPMF_E_NOMEM. */
+bpmf_status bpmf_server_create(bpmf_server **srv, const bpmf_foldin_model *m,
+                               size_t mem_budget_bytes, int32_t n_streams, int32_t max_batch,
+                               int32_t max_inflight);
+
+/* Queues one request (host arrays: nnz column indices in [0, N) and ratings,
+ * nq query columns in [0, N)).  BPMF_E_INVALID if an index is out of range or
+ * the request alone exceeds one stream's share of the budget. */
+bpmf_status bpmf_server_submit(bpmf_server *srv, int64_t id, int32_t nnz, const int32_t *h_cols,
+                               const float *h_vals, int32_t nq, const int32_t *h_q_cols);
+
+/* Moves up to max_results finished requests out of the server: ids[i], the
+ * predictions of request i at h_preds[offsets[i] .. offsets[i+1]) (offsets
+ * has max_results + 1 entries, h_preds room for pred_capacity floats) and its
+ * latency in seconds from submit to the host seeing the result.  *n_out
+ * receives the number of results moved. Never blocks. */
+bpmf_status bpmf_server_poll(bpmf_server *srv, int32_t max_results, int64_t *ids, int64_t *offsets,
+                             float *h_preds, int64_t pred_capacity, double *latency_s,
+                             int32_t *n_out);
+
+/* Blocks until every submitted request has finished (results stay pollable). */
+bpmf_status bpmf_server_drain(bpmf_server *srv);
+
+bpmf_status bpmf_server_get_stats(bpmf_server *srv, bpmf_server_stats *st);
+
+/* Real-time replay of an arrival trace: a client thread submits request i at
+ * arrival_s[i] seconds after the call starts (requests in CSR form: ratings
+ * h_cols/h_vals[h_ptr[i] .. h_ptr[i+1]), queries h_q_cols[h_q_ptr[i] ..
+ * h_q_ptr[i+1])), then the call waits for all of them and writes each
+ * request's predictions to h_out[h_q_ptr[i] ..] and its latency to
+ * latency_s[i].  Requests are identified by their index. */
+bpmf_status bpmf_server_replay(bpmf_server *srv, int64_t n, const double *arrival_s,
+                               const int64_t *h_ptr, const int32_t *h_cols, const float *h_vals,
+                               const int64_t *h_q_ptr, const int32_t *h_q_cols, float *h_out,
+                               double *latency_s);
+
+bpmf_status bpmf_server_destroy(bpmf_server *srv);
+
+/* ------------------------------------------------------------------------ */
 /* Misc                                                                      */
 /* ------------------------------------------------------------------------ */
 const char *bpmf_status_string(bpmf_status s);

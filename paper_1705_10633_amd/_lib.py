@@ -46,6 +46,11 @@ class FoldinModel(C.Structure):
                 ("d_V", P), ("d_Lambda", P), ("d_mu", P)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("requests_done", I64), ("batches", I64), ("max_batch", I64), ("max_inflight", I64),
+                ("max_batch_bytes", I64), ("stream_capacity", I64)]
+
+
 TIMING_CLASSES = ("stats", "hyper", "rows_users", "rows_movies", "fp64_recompute", "predict", "counter")
 
 
@@ -78,6 +83,13 @@ EXPORTS = {
     "bpmf_get_timing": [P, P, I32],
     "bpmf_foldin_workspace_size": [P, I64, P],
     "bpmf_foldin": [P, I64, P, P, P, P, P, I64, P, P, SZ, P],
+    "bpmf_server_create": [P, P, SZ, I32, I32, I32],
+    "bpmf_server_submit": [P, I64, I32, P, P, I32, P],
+    "bpmf_server_poll": [P, I32, P, P, P, I64, P, P],
+    "bpmf_server_drain": [P],
+    "bpmf_server_get_stats": [P, P],
+    "bpmf_server_replay": [P, I64, P, P, P, P, P, P, P, P],
+    "bpmf_server_destroy": [P],
     "bpmf_status_string": [I32],
     "bpmf_last_error": [],
     "bpmf_version": [],

@@ -38,6 +38,8 @@ using namespace bpmf;
 
 static thread_local std::string g_last_error;
 
+void bpmf::set_last_error(const std::string &msg) { g_last_error = msg; }
+
 static bpmf_status fail(bpmf_status s, const std::string &msg)
 {
     g_last_error = msg;

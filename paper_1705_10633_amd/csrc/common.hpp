@@ -3,7 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace bpmf {
+
+// Sets the thread-local message returned by bpmf_last_error().
+void set_last_error(const std::string &msg);
 
 // Where a half-sweep's standard normals come from: a tape block (row-major
 // n x K doubles) or the device counter-based generator at half-sweep

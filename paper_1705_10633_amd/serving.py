@@ -1,0 +1,114 @@
+"""Fold-in serving: the native continuous-batching engine of libbpmf
+(bpmf_server_*), its Python handle, and the latency benchmark of the
+S = 16 x 20,000 x 64 fold-in workload."""
+from __future__ import annotations
+
+import ctypes as C
+import time
+
+import numpy as np
+
+from . import _lib
+from ._lib import call
+
+
+class FoldinServer:
+    """Continuous-batching fold-in server over stored posterior samples
+    (a sampler.Foldin holding the device arrays)."""
+
+    def __init__(self, foldin, mem_budget_bytes=256 << 20, n_streams=4, max_batch=256,
+                 max_inflight=4096):
+        self.foldin = foldin  # keeps the model's device arrays alive
+        self.srv = C.c_void_p()
+        call("bpmf_server_create", C.byref(self.srv), C.byref(foldin.model), C.c_size_t(mem_budget_bytes),
+             n_streams, max_batch, max_inflight)
+
+    def close(self):
+        if self.srv:
+            _lib.load().bpmf_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, rid, cols, vals, q_cols):
+        cols = np.ascontiguousarray(cols, np.int32)
+        vals = np.ascontiguousarray(vals, np.float32)
+        q = np.ascontiguousarray(q_cols, np.int32)
+        call("bpmf_server_submit", self.srv, int(rid), cols.size, cols.ctypes.data, vals.ctypes.data,
+             q.size, q.ctypes.data)
+
+    def drain(self):
+        call("bpmf_server_drain", self.srv)
+
+    def poll(self, max_results=4096, pred_capacity=1 << 22):
+        ids = np.empty(max_results, np.int64)
+        off = np.empty(max_results + 1, np.int64)
+        preds = np.empty(pred_capacity, np.float32)
+        lat = np.empty(max_results)
+        n = C.c_int32()
+        call("bpmf_server_poll", self.srv, max_results, ids.ctypes.data, off.ctypes.data, preds.ctypes.data,
+             pred_capacity, lat.ctypes.data, C.byref(n))
+        k = n.value
+        return [(int(ids[i]), preds[off[i]:off[i + 1]].copy(), float(lat[i])) for i in range(k)]
+
+    def stats(self):
+        st = _lib.ServerStats()
+        call("bpmf_server_get_stats", self.srv, C.byref(st))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def replay(self, req):
+        """Replays a synth.FoldinRequests trace in real time; returns (predictions, latencies)."""
+        n = req.n
+        out = np.empty(max(int(req.q_ptr[-1]), 1), np.float32)
+        lat = np.empty(max(n, 1))
+        arr = np.ascontiguousarray(req.arrival, np.float64)
+        ptr = np.ascontiguousarray(req.ptr, np.int64)
+        cols = np.ascontiguousarray(req.cols, np.int32)
+        vals = np.ascontiguousarray(req.vals, np.float32)
+        qp = np.ascontiguousarray(req.q_ptr, np.int64)
+        qc = np.ascontiguousarray(req.q_cols, np.int32)
+        call("bpmf_server_replay", self.srv, n, arr.ctypes.data, ptr.ctypes.data, cols.ctypes.data,
+             vals.ctypes.data, qp.ctypes.data, qc.ctypes.data, out.ctypes.data, lat.ctypes.data)
+        return out[: int(req.q_ptr[-1])], lat[:n]
+
+
+def bench_foldin(seconds=2.0, rates=(5000, 10000, 20000, 50000), S=16, N=20000, K=64, Q=100,
+                 n_streams=4, mem_budget=256 << 20, max_batch=256, log=print):
+    """p50 / p99 latency of Poisson request streams against S stored samples."""
+    from . import synth
+    from .sampler import Foldin
+    model = synth.foldin_model(S=S, N=N, K=K)
+    fm = Foldin(model.Vs, model.Lambda, model.mu, model.alpha, model.mean_rating)
+    out = {"model": f"S={S} samples of V ({N} x {K}, FP32) resident on device",
+           "request": "log-normal(3, 1.5) ratings clipped to 1..5000 over distinct columns, "
+                      f"ratings N(3,1), Q={Q} query columns",
+           "memory_budget_bytes": mem_budget, "n_streams": n_streams, "max_batch": max_batch,
+           "rates": {}}
+    for rate in rates:
+        n = int(rate * seconds)
+        t0 = time.perf_counter()
+        req = synth.foldin_requests(n, N, seed=105, Q=Q, rate=rate, stream_offset=rate)
+        gen = time.perf_counter() - t0
+        srv = FoldinServer(fm, mem_budget_bytes=mem_budget, n_streams=n_streams, max_batch=max_batch)
+        # warm-up burst
+        warm = synth.foldin_requests(64, N, seed=7, Q=Q, rate=rate, stream_offset=1)
+        srv.replay(warm)
+        t0 = time.perf_counter()
+        _, lat = srv.replay(req)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat_ms = lat * 1e3
+        rec = {"requests": n, "offered_rps": rate, "achieved_rps": n / wall,
+               "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+               "p999_ms": float(np.percentile(lat_ms, 99.9)), "max_ms": float(lat_ms.max()),
+               "batches": st["batches"], "mean_batch": st["requests_done"] / max(st["batches"], 1),
+               "max_batch": st["max_batch"], "max_inflight": st["max_inflight"]}
+        out["rates"][str(rate)] = rec
+        log(f"[serve] {rate:6d} req/s: p50 {rec['p50_ms']:.3f} ms p99 {rec['p99_ms']:.3f} ms "
+            f"(mean batch {rec['mean_batch']:.1f}, achieved {rec['achieved_rps']:.0f} req/s, gen {gen:.1f} s)")
+    return out
