@@ -28,8 +28,8 @@ hipError_t launch_foldin(int S, int K, int64_t N, double alpha, double rbar, con
                          hipStream_t st);
 hipError_t launch_sum_values(const void *vals, int is_f64, int64_t n, double *partials, int nblk,
                              hipStream_t s);
-hipError_t launch_mean_from_sum(const double *accum, int64_t n, const DevState *state, double *out,
-                                hipStream_t s);
+hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_t n,
+                                const DevState *state, double *out, hipStream_t s);
 hipError_t prepare_rows_f64(int K);
 hipError_t prepare_nw(int K);
 }  // namespace bpmf
@@ -67,7 +67,7 @@ struct WsLayout {
 
 struct Offsets {
     size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], mu0, w0inv,
-        order[2], fblist[2], shadow[2], valsf[2], accum, reduce;
+        order[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
 
@@ -102,6 +102,9 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
     o.mu0 = w.add(sizeof(double) * K);
     o.w0inv = w.add(sizeof(double) * K * K);
     o.accum = w.add(sizeof(double) * std::max<int64_t>(n_test, 0));
+    o.trows = w.add(sizeof(int32_t) * std::max<int64_t>(n_test, 0));
+    o.tcols = w.add(sizeof(int32_t) * std::max<int64_t>(n_test, 0));
+    o.tperm = w.add(sizeof(int64_t) * std::max<int64_t>(n_test, 0));
     o.reduce = w.add(sizeof(double) * 1024);
     o.total = w.total + kAlign;
     return o;
@@ -123,6 +126,8 @@ struct bpmf_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
+    hipStream_t aux = nullptr;  // second stream for the overlapped hyper step
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool broken = false;
     // per-kernel timing
     bool timing = false;
@@ -344,6 +349,9 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         if (_e != hipSuccess) return bail(fail(BPMF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e))); \
     } while (0)
 
+    HIP_OK_C(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIP_OK_C(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIP_OK_C(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIP_OK_C(prepare_rows_f64(K));
     HIP_OK_C(prepare_nw(K));
     HIP_OK_C(launch_fill_zero(c->ws, off.total - kAlign, s));
@@ -375,6 +383,30 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
             return pp[a + 1] - pp[a] > pp[b + 1] - pp[b];
         });
         HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.order[sd]), ord.data(), sizeof(int32_t) * n[sd], hipMemcpyHostToDevice, s));
+        HIP_OK_C(hipStreamSynchronize(s));
+    }
+    // held-out pairs sorted by user (then movie) so that predictions reuse rows
+    if (n_test > 0) {
+        std::vector<int32_t> tr(n_test), tc(n_test);
+        HIP_OK_C(hipMemcpyAsync(tr.data(), d_test_rows, 4 * n_test, hipMemcpyDeviceToHost, s));
+        HIP_OK_C(hipMemcpyAsync(tc.data(), d_test_cols, 4 * n_test, hipMemcpyDeviceToHost, s));
+        HIP_OK_C(hipStreamSynchronize(s));
+        for (int64_t t = 0; t < n_test; ++t)
+            if (tr[t] < 0 || tr[t] >= R->M || tc[t] < 0 || tc[t] >= R->N)
+                return bail(fail(BPMF_E_INVALID, "test pair out of range at " + std::to_string(t)));
+        std::vector<int64_t> perm(n_test);
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
+            return tr[a] != tr[b] ? tr[a] < tr[b] : tc[a] < tc[b];
+        });
+        std::vector<int32_t> sr(n_test), sc(n_test);
+        for (int64_t t = 0; t < n_test; ++t) {
+            sr[t] = tr[perm[t]];
+            sc[t] = tc[perm[t]];
+        }
+        HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.trows), sr.data(), 4 * n_test, hipMemcpyHostToDevice, s));
+        HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.tcols), sc.data(), 4 * n_test, hipMemcpyHostToDevice, s));
+        HIP_OK_C(hipMemcpyAsync(c->at<int64_t>(off.tperm), perm.data(), 8 * n_test, hipMemcpyHostToDevice, s));
         HIP_OK_C(hipStreamSynchronize(s));
     }
     // priors
@@ -431,25 +463,26 @@ static void time_end(bpmf_ctx *c, int cls, hipEvent_t a, hipStream_t s)
     c->pending.push_back({cls, {a, b}});
 }
 
-// One half-sweep on stream s.
-static bpmf_status enqueue_half(bpmf_ctx *c, int side, const double *tape_block, hipStream_t s)
+static DrawSrc draws_for(bpmf_ctx *c, int side, const double *tape_block)
 {
     const int K = c->K;
-    const bpmf_ratings &R = c->R;
-    const int64_t n = side == 0 ? R.M : R.N;
-    void *X = side == 0 ? c->dU : c->dV;
-    void *other = side == 0 ? c->dV : c->dU;
-    const bool f64 = c->precision == BPMF_FP64;
-    const bool mixed_kernel = !f64 && mixed_supported(K);
     DrawSrc d;
     d.tape_nw = tape_block;
     d.tape_rows = tape_block ? tape_block + K + K * (K - 1) / 2 + K : nullptr;
     d.seed = c->seed;
     d.sweep = &c->state->sweep;
     d.side = side;
+    return d;
+}
 
+// Hyper-parameters of one side from that side's current factors (stream s).
+static bpmf_status enqueue_hyper(bpmf_ctx *c, int side, const DrawSrc &d, hipStream_t s)
+{
+    const int K = c->K;
+    const int64_t n = side == 0 ? c->R.M : c->R.N;
+    void *X = side == 0 ? c->dU : c->dV;
     hipEvent_t t0 = time_begin(c, s);
-    HIP_OK(launch_stats(X, f64 ? 1 : 0, n, K, c->at<double>(c->off.partials[side]), c->n_chunks[side], s));
+    HIP_OK(launch_stats(X, c->x_f64() ? 1 : 0, n, K, c->at<double>(c->off.partials[side]), c->n_chunks[side], s));
     HIP_OK(launch_stats_reduce(c->at<double>(c->off.partials[side]), c->n_chunks[side], K,
                                c->at<double>(c->off.sums[side]), s));
     time_end(c, 0, t0, s);
@@ -458,16 +491,27 @@ static bpmf_status enqueue_half(bpmf_ctx *c, int side, const double *tape_block,
                      c->at<double>(c->off.w0inv), d, c->at<double>(c->off.scratch[side]), c->hyp[side],
                      K <= 64 ? 1 : 0, c->state, s));
     time_end(c, 1, t0, s);
+    return BPMF_OK;
+}
 
+// Row updates of one side given the other side (stream s).
+static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStream_t s)
+{
+    const int K = c->K;
+    const bpmf_ratings &R = c->R;
+    const int64_t n = side == 0 ? R.M : R.N;
+    const bool f64 = c->precision == BPMF_FP64;
+    const bool mixed_kernel = !f64 && mixed_supported(K);
     SideArgs a;
     a.n_rows = n;
     a.ptr = side == 0 ? R.d_row_ptr : R.d_col_ptr;
     a.idx = side == 0 ? R.d_col_idx : R.d_row_idx;
     const void *vals_orig = side == 0 ? R.d_row_val : R.d_col_val;
-    a.X = X;
-    a.other = other;
+    a.X = side == 0 ? c->dU : c->dV;
+    a.other = side == 0 ? c->dV : c->dU;
     a.order = c->at<int32_t>(c->off.order[side]);
     a.shadow_stride = c->KP;
+    hipEvent_t t0;
     if (f64) {
         a.val = vals_orig;
         a.val_is_f64 = R.val_is_f64;
@@ -502,18 +546,32 @@ static bpmf_status enqueue_half(bpmf_ctx *c, int side, const double *tape_block,
     return BPMF_OK;
 }
 
+// One sweep.  The movies' hyper-parameters depend only on V, which the
+// users' half does not change, so they are computed on the auxiliary stream
+// while the users' rows are updated; the movies' rows wait for both.
 static bpmf_status enqueue_sweep(bpmf_ctx *c, const double *tape, hipStream_t s)
 {
     const int K = c->K;
     const int64_t hb = (int64_t)K + (int64_t)K * (K - 1) / 2 + K;
-    bpmf_status st = enqueue_half(c, 0, tape, s);
+    const DrawSrc d0 = draws_for(c, 0, tape);
+    const DrawSrc d1 = draws_for(c, 1, tape ? tape + hb + c->R.M * K : nullptr);
+    HIP_OK(hipEventRecord(c->ev_fork, s));
+    HIP_OK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+    bpmf_status st = enqueue_hyper(c, 1, d1, c->aux);
     if (st != BPMF_OK) return st;
-    st = enqueue_half(c, 1, tape ? tape + hb + c->R.M * K : nullptr, s);
+    HIP_OK(hipEventRecord(c->ev_join, c->aux));
+    st = enqueue_hyper(c, 0, d0, s);
+    if (st != BPMF_OK) return st;
+    st = enqueue_rows(c, 0, d0, s);
+    if (st != BPMF_OK) return st;
+    HIP_OK(hipStreamWaitEvent(s, c->ev_join, 0));
+    st = enqueue_rows(c, 1, d1, s);
     if (st != BPMF_OK) return st;
     if (c->n_test > 0) {
         hipEvent_t t0 = time_begin(c, s);
-        HIP_OK(launch_predict(c->dU, c->dV, c->x_f64() ? 1 : 0, K, c->rbar, c->n_test, c->test_rows,
-                              c->test_cols, nullptr, c->at<double>(c->off.accum), c->state, c->burnin, s));
+        HIP_OK(launch_predict(c->dU, c->dV, c->x_f64() ? 1 : 0, K, c->rbar, c->n_test,
+                              c->at<int32_t>(c->off.trows), c->at<int32_t>(c->off.tcols), nullptr,
+                              c->at<double>(c->off.accum), c->state, c->burnin, s));
         time_end(c, 5, t0, s);
     }
     hipEvent_t t1 = time_begin(c, s);
@@ -578,7 +636,8 @@ bpmf_status bpmf_test_predictions(bpmf_ctx *c, double *d_mean, int64_t *h_count,
     hipStream_t s = (hipStream_t)stream;
     if (c->n_test > 0) {
         if (!d_mean) return fail(BPMF_E_INVALID, "NULL d_mean");
-        HIP_OK(launch_mean_from_sum(c->at<double>(c->off.accum), c->n_test, c->state, d_mean, s));
+        HIP_OK(launch_mean_from_sum(c->at<double>(c->off.accum), c->at<int64_t>(c->off.tperm), c->n_test,
+                                    c->state, d_mean, s));
     }
     DevState h;
     HIP_OK(hipMemcpyAsync(&h, c->state, sizeof(DevState), hipMemcpyDeviceToHost, s));
@@ -737,6 +796,9 @@ bpmf_status bpmf_destroy(bpmf_ctx *c)
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->graph) hipGraphDestroy(c->graph);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    if (c->aux) hipStreamDestroy(c->aux);
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
     delete c;
     return BPMF_OK;
 }

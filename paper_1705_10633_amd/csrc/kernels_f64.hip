@@ -262,8 +262,104 @@ __global__ __launch_bounds__(256) void stats_kernel(const XT *X, int64_t n, int 
     }
 }
 
-// 16 lanes per pair: coalesced reads of both factor rows, FP64 accumulation,
-// shuffle reduction inside the 16-lane group.
+// Side statistics on FP64 matrix cores (K <= 64): one wavefront per chunk of
+// rows; every 4 rows feed v_mfma_f64_16x16x4_f64 for each lower 16x16 tile
+// of sum x x^T (operand lane l = row l/16 of the group, feature l%16 of the
+// block; accumulator lane l, element v = tile row 4v + l/16, column l%16).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename XT, int NB>
+__global__ __launch_bounds__(256) void stats_mfma_kernel(const XT *X, int64_t n, int K, double *partials,
+                                                         int n_chunks)
+{
+    constexpr int NT = NB * (NB + 1) / 2;
+    constexpr int PER_WAVE = (4 * NT + NB) * 64;  // doubles one wave contributes to the reduction
+    __shared__ double red[2][PER_WAVE];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r0 = n * blockIdx.x / n_chunks, r1 = n * (blockIdx.x + 1) / n_chunks;
+    const int i16 = lane & 15, g = lane >> 4;
+    f64x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double sx[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) sx[b] = 0.0;
+    // wave w takes row groups r0 + 4 (w + 4 i), GB groups at a time: all their
+    // loads are issued before any of them is multiplied
+    constexpr int GB = 8;
+    for (int64_t q0 = r0 + 4 * wave; q0 < r1; q0 += 16 * GB) {
+        double x[GB][NB];
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            const int64_t r = q0 + 16 * u + g;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int f = 16 * b + i16;
+                x[u][b] = (r < r1 && f < K) ? (double)X[r * K + f] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            int t = 0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b, ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u][a], x[u][b], acc[t], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) sx[b] += x[u][b];
+        }
+    }
+    // fixed-order reduction of the four waves: (0 + 2) + (1 + 3), then 0 + 1
+    auto put = [&](double *dst) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[(t * 4 + v) * 64 + lane] = acc[t][v];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) dst[(4 * NT + b) * 64 + lane] = sx[b];
+    };
+    auto add = [&](const double *src) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][v] += src[(t * 4 + v) * 64 + lane];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) sx[b] += src[(4 * NT + b) * 64 + lane];
+    };
+    if (wave >= 2) put(red[wave - 2]);
+    __syncthreads();
+    if (wave < 2) add(red[wave]);
+    __syncthreads();
+    if (wave == 1) put(red[0]);
+    __syncthreads();
+    if (wave != 0) return;
+    add(red[0]);
+    const int E = K + K * (K + 1) / 2;
+    double *out = partials + (int64_t)blockIdx.x * E;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        double v = sx[b];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        const int f = 16 * b + i16;
+        if (g == 0 && f < K) out[f] = v;
+    }
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b, ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = 16 * a + 4 * v + g, cc = 16 * b + i16;
+                if (rr < K && cc <= rr) out[K + rr * (rr + 1) / 2 + cc] = acc[t][v];
+            }
+}
+
+// 16 lanes per group of 4 consecutive (row-sorted) pairs: all eight factor
+// row reads of a lane are issued together, FP64 accumulation, shuffle
+// reduction inside the 16-lane group.
 template <typename XT>
 __global__ __launch_bounds__(256) void predict_kernel(const XT *U, const XT *V, int K, double rbar,
                                                       int64_t n, const int32_t *rows,
@@ -271,20 +367,40 @@ __global__ __launch_bounds__(256) void predict_kernel(const XT *U, const XT *V, 
                                                       double *accum, const DevState *state,
                                                       int burnin)
 {
-    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    constexpr int PP = 4;
+    const int64_t t0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4) * PP;
     const int l = threadIdx.x & 15;
-    double p = 0.0;
-    if (t < n) {
-        const XT *u = U + (int64_t)rows[t] * K;
-        const XT *v = V + (int64_t)cols[t] * K;
-        for (int f = l; f < K; f += 16) p = fma((double)u[f], (double)v[f], p);
+    double p[PP];
+    const XT *u[PP], *v[PP];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        p[q] = 0.0;
+        const int64_t t = t0 + q < n ? t0 + q : n - 1;
+        u[q] = U + (int64_t)rows[t] * K;
+        v[q] = V + (int64_t)cols[t] * K;
+    }
+    for (int f = l; f < K; f += 16) {
+        XT a[PP], b[PP];
+#pragma unroll
+        for (int q = 0; q < PP; ++q) {
+            a[q] = u[q][f];
+            b[q] = v[q][f];
+        }
+#pragma unroll
+        for (int q = 0; q < PP; ++q) p[q] = fma((double)a[q], (double)b[q], p[q]);
     }
 #pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) p += __shfl_xor(p, o, 16);
-    if (t < n && l == 0) {
-        p += rbar;
-        if (out) out[t] = p;
-        if (accum && state->sweep >= burnin) accum[t] += p;
+    for (int q = 0; q < PP; ++q)
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) p[q] += __shfl_xor(p[q], o, 16);
+    if (l < PP && t0 + l < n) {
+        double r = p[0];
+#pragma unroll
+        for (int q = 1; q < PP; ++q) r = (l == q) ? p[q] : r;
+        r += rbar;
+        const int64_t t = t0 + l;
+        if (out) out[t] = r;
+        if (accum && state->sweep >= burnin) accum[t] += r;
     }
 }
 
@@ -314,12 +430,13 @@ __global__ void sum_values_kernel(const VT *v, int64_t n, double *partials)
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-__global__ void mean_from_sum_kernel(const double *accum, int64_t n, const DevState *state, double *out)
+__global__ void mean_from_sum_kernel(const double *accum, const int64_t *perm, int64_t n,
+                                     const DevState *state, double *out)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int64_t c = state->pred_count;
-    out[t] = c > 0 ? accum[t] / (double)c : 0.0;
+    out[perm[t]] = c > 0 ? accum[t] / (double)c : 0.0;
 }
 
 __global__ void reset_fb_kernel(DevState *s, int side)
@@ -419,18 +536,38 @@ hipError_t launch_sum_values(const void *vals, int is_f64, int64_t n, double *pa
     return hipGetLastError();
 }
 
-hipError_t launch_mean_from_sum(const double *accum, int64_t n, const DevState *state, double *out, hipStream_t s)
+hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_t n, const DevState *state,
+                                double *out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mean_from_sum_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, accum, n, state, out);
+    hipLaunchKernelGGL(mean_from_sum_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, accum, perm, n, state, out);
     return hipGetLastError();
 }
 
-int stats_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 255) / 256)); }
+int stats_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 511) / 512)); }
 
 hipError_t launch_stats(const void *X, int x_is_f64, int64_t n, int K, double *partials,
                         int n_chunks, hipStream_t s)
 {
+    if (K <= 64) {
+        const int NB = (K + 15) / 16;
+#define BPMF_STATS_MFMA(XT, NBV)                                                                        \
+    hipLaunchKernelGGL((stats_mfma_kernel<XT, NBV>), dim3(n_chunks), dim3(256), 0, s, (const XT *)X, n, K, \
+                       partials, n_chunks)
+        if (x_is_f64) {
+            if (NB == 1) BPMF_STATS_MFMA(double, 1);
+            else if (NB == 2) BPMF_STATS_MFMA(double, 2);
+            else if (NB == 3) BPMF_STATS_MFMA(double, 3);
+            else BPMF_STATS_MFMA(double, 4);
+        } else {
+            if (NB == 1) BPMF_STATS_MFMA(float, 1);
+            else if (NB == 2) BPMF_STATS_MFMA(float, 2);
+            else if (NB == 3) BPMF_STATS_MFMA(float, 3);
+            else BPMF_STATS_MFMA(float, 4);
+        }
+#undef BPMF_STATS_MFMA
+        return hipGetLastError();
+    }
     const int nb = (K + 3) >> 2;
     const bool big = nb * (nb + 1) / 2 > 256;
     if (x_is_f64) {
@@ -449,10 +586,10 @@ hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, dou
 {
     if (n <= 0) return hipSuccess;
     if (x_is_f64)
-        hipLaunchKernelGGL(predict_kernel<double>, dim3(grid_for(n * 16, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(predict_kernel<double>, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
                            (const double *)U, (const double *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
     else
-        hipLaunchKernelGGL(predict_kernel<float>, dim3(grid_for(n * 16, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(predict_kernel<float>, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
                            (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
     return hipGetLastError();
 }

@@ -39,8 +39,16 @@ __global__ __launch_bounds__(256) void stats_reduce_kernel(const double *partial
     const int part = threadIdx.x & 7;
     double s = 0.0;
     if (e < E) {
+        // four independent accumulators (fixed assignment c % 4), combined in order
         const int c0 = n_chunks * part / 8, c1 = n_chunks * (part + 1) / 8;
-        for (int c = c0; c < c1; ++c) s += partials[(int64_t)c * E + e];
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        int c = c0;
+        for (; c + 4 <= c1; c += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s4[u] += partials[(int64_t)(c + u) * E + e];
+        }
+        for (int u = 0; c < c1; ++c, ++u) s4[u] += partials[(int64_t)c * E + e];
+        s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     s += __shfl_xor(s, 4, 8);
     s += __shfl_xor(s, 2, 8);
@@ -120,25 +128,58 @@ __global__ __launch_bounds__(NW_THREADS) void nw_kernel(const double *sums, int6
         }
     }
     __syncthreads();
-    // T: R^T T = A, one thread per column of A (both lower triangular)
-    for (int c = tid; c < K; c += NW_THREADS) {
-        for (int i = 0; i < c; ++i) M2[i * K + c] = 0.0;
-        for (int i = c; i < K; ++i) {
-            double s = (i == c) ? sqrt(chi2[c]) : zb[i * (i - 1) / 2 + c];
-            for (int m = c; m < i; ++m) s = fma(-M1[m * K + i], M2[m * K + c], s);
-            M2[i * K + c] = s / rd[i];
+    // T: R^T T = A (both lower triangular), right-looking: step m fixes row m
+    // of T and removes its contribution from the rows below.  M2 starts as A.
+    for (int e = tid; e < KK; e += NW_THREADS) {
+        const int i = e / K, c = e - i * K;
+        M2[e] = (c > i) ? 0.0 : ((i == c) ? sqrt(chi2[c]) : zb[i * (i - 1) / 2 + c]);
+    }
+    for (int m = 0; m < K; ++m) {
+        __syncthreads();
+        const double irm = 1.0 / rd[m];
+        // rows i > m, columns c <= m: M2[i][c] -= R_mi T_mc, with T_mc = M2[m][c] / R_mm
+        const int rows = K - 1 - m, cols = m + 1;
+        for (int e = tid; e < rows * cols; e += NW_THREADS) {
+            const int ii = e / cols, c = e - ii * cols;
+            const int i = m + 1 + ii;
+            M2[i * K + c] = fma(-M1[m * K + i], M2[m * K + c] * irm, M2[i * K + c]);
         }
+        __syncthreads();
+        for (int c = tid; c <= m; c += NW_THREADS) M2[m * K + c] *= irm;
     }
     __syncthreads();
-    // Lambda = T T^T
-    for (int e = tid; e < KK; e += NW_THREADS) {
-        const int a = e / K, c = e - a * K;
-        const int m1 = a < c ? a : c;
-        double s = 0.0;
-        for (int m = 0; m <= m1; ++m) s = fma(M2[a * K + m], M2[c * K + m], s);
-        M1[e] = s;
-        hyp.Lambda[e] = s;
-        hyp.Lambda_f[e] = (float)s;
+    // Lambda = T T^T in 4x4 register tiles (T[a][m] = 0 for m > a)
+    {
+        const int nb = (K + 3) / 4;
+        for (int tb = tid; tb < nb * nb; tb += NW_THREADS) {
+            const int ba = tb / nb, bc = tb - ba * nb;
+            double acc[4][4] = {};
+            const int mmax = min(K, 4 * min(ba, bc) + 4);
+            for (int m = 0; m < mmax; ++m) {
+                double ta[4], tc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int a = 4 * ba + q, c = 4 * bc + q;
+                    ta[q] = a < K ? M2[a * K + m] : 0.0;
+                    tc[q] = c < K ? M2[c * K + m] : 0.0;
+                }
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = fma(ta[x], tc[y], acc[x][y]);
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    const int a = 4 * ba + x, c = 4 * bc + y;
+                    if (a < K && c < K) {
+                        M1[a * K + c] = acc[x][y];
+                        hyp.Lambda[a * K + c] = acc[x][y];
+                        hyp.Lambda_f[a * K + c] = (float)acc[x][y];
+                    }
+                }
+        }
     }
     // mean: T^T d = z / sqrt(beta*), column-oriented backward substitution
     const double isb = 1.0 / sqrt(bstar);

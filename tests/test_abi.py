@@ -1,0 +1,132 @@
+"""The C ABI without a GPU: every function include/bpmf.h declares is exported
+by libbpmf.so, and the host-side validation of parameters returns the
+documented status codes (these calls never touch the device)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bpmf.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1705_10633_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1705_10633_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bpmf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("bpmf_init", "bpmf_sweep", "bpmf_predict", "bpmf_foldin", "bpmf_workspace_size",
+                     "bpmf_server_create", "bpmf_server_replay"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the Python binding declares argument types for all of them
+    from paper_1705_10633_amd import _lib
+    assert set(declared_functions()) <= set(_lib.EXPORTS), set(declared_functions()) - set(_lib.EXPORTS)
+
+
+def test_status_strings(lib):
+    for code in range(7):
+        assert lib.bpmf_status_string(code)
+    assert lib.bpmf_version().startswith(b"bpmf")
+
+
+def _params(K=4, nu0=None, W0=None, mu0=None, alpha=2.0, beta0=2.0, precision=0):
+    from paper_1705_10633_amd import _lib
+    mu0 = np.zeros(K) if mu0 is None else mu0
+    W0 = np.eye(K) if W0 is None else W0
+    keep = (np.ascontiguousarray(mu0, np.float64), np.ascontiguousarray(W0, np.float64))
+    p = _lib.Params(K, precision, alpha, beta0, float(K) if nu0 is None else nu0, keep[0].ctypes.data,
+                    keep[1].ctypes.data, float("nan"), 0, 0, 0, 0)
+    return p, keep
+
+
+def _ratings(M=10, N=8, nnz=20):
+    from paper_1705_10633_amd import _lib
+    fake = 0x1000  # never dereferenced by bpmf_workspace_size
+    return _lib.Ratings(M, N, nnz, fake, fake, fake, fake, fake, fake, 0)
+
+
+def _ws(lib, R, p, n_test=0):
+    n = C.c_size_t()
+    st = lib.bpmf_workspace_size(C.byref(R), C.byref(p), n_test, C.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_validates_parameters(lib):
+    R = _ratings()
+    p, keep = _params()
+    st, n = _ws(lib, R, p)
+    assert st == 0 and n > 0
+    st, n2 = _ws(lib, R, p, n_test=1000)
+    assert st == 0 and n2 >= n + 8 * 1000
+    for K in (0, 129):
+        p, keep = _params(K=max(K, 1))
+        p.K = K
+        assert _ws(lib, R, p)[0] == 1, K
+    p, keep = _params(K=4, nu0=2.9)          # nu0 must exceed K - 1
+    assert _ws(lib, R, p)[0] == 1
+    p, keep = _params(alpha=0.0)
+    assert _ws(lib, R, p)[0] == 1
+    p, keep = _params(beta0=-1.0)
+    assert _ws(lib, R, p)[0] == 1
+    p, keep = _params(mu0=np.array([0.0, math.nan, 0.0, 0.0]))
+    assert _ws(lib, R, p)[0] == 1
+    W = np.eye(4)
+    W[0, 1] = 0.3
+    p, keep = _params(W0=W)                   # not symmetric
+    assert _ws(lib, R, p)[0] == 2
+    W = np.eye(4)
+    W[3, 3] = -1.0
+    p, keep = _params(W0=W)                   # not positive definite
+    assert _ws(lib, R, p)[0] == 2
+    assert b"positive definite" in lib.bpmf_last_error()
+    p, keep = _params(precision=3)
+    assert _ws(lib, R, p)[0] == 1
+    p, keep = _params()
+    bad = _ratings(M=0)
+    assert _ws(lib, bad, p)[0] == 1
+    from paper_1705_10633_amd import _lib
+    nulls = _lib.Ratings(10, 8, 20, 0x1000, None, None, 0x1000, None, None, 0)
+    assert _ws(lib, nulls, p)[0] == 1
+
+
+def test_null_context_is_rejected(lib):
+    assert lib.bpmf_sweep(None, 1, None, 0, None) == 4
+    assert lib.bpmf_predict(None, 0, None, None, None, None) == 4
+    assert lib.bpmf_destroy(None) == 0
+    assert lib.bpmf_server_destroy(None) == 0
+    assert lib.bpmf_server_submit(None, 0, 0, None, None, 0, None) == 4
+
+
+def test_foldin_and_server_argument_checks(lib):
+    from paper_1705_10633_amd import _lib
+    fake = 0x1000
+    m = _lib.FoldinModel(16, 64, 20000, 2.0, 3.0, fake, fake, fake)
+    n = C.c_size_t()
+    assert lib.bpmf_foldin_workspace_size(C.byref(m), 100, C.byref(n)) == 0
+    assert n.value == 4 * 16 * 100
+    bad = _lib.FoldinModel(16, 65, 20000, 2.0, 3.0, fake, fake, fake)   # K > 64
+    assert lib.bpmf_foldin(C.byref(bad), 1, fake, fake, fake, fake, fake, 1, fake, fake, 1 << 20, None) == 1
+    srv = C.c_void_p()
+    assert lib.bpmf_server_create(C.byref(srv), C.byref(bad), 1 << 20, 2, 8, 8) == 1
+    assert lib.bpmf_server_create(C.byref(srv), C.byref(m), 1 << 20, 0, 8, 8) == 1     # no streams
+    assert lib.bpmf_server_create(C.byref(srv), C.byref(m), 64, 1, 8, 8) == 1          # budget too small

@@ -132,16 +132,18 @@ def test_mixed_one_sweep_error(precision, K):
 
 
 def test_fp32_pivot_failure_falls_back_to_fp64():
-    """Huge alpha with single-rating rows makes the FP32 pivots after the first
-    one fall under 64 K 2^-24 max P_kk; those rows are recomputed in FP64 from
-    the FP32 factors and then agree with the FP64 oracle to FP64 accuracy."""
+    """With one rating per user and alpha = 1e9, P = Lambda + alpha v v^T has a
+    largest diagonal ~ alpha |v|^2 ~ 1e7 while the pivots after the first are
+    ~ Lambda_kk ~ 1e2, below 64 K 2^-24 max P_kk ~ 6e2: every user row is
+    flagged (the identity padding of K = 16 up to 32 is not), recomputed in
+    FP64 from the FP32 factors, and agrees with the FP64 oracle."""
     M, N, K = 200, 150, 16
     rng = np.random.default_rng(5)
     rows = np.arange(M)
     cols = rng.integers(0, N, M)
     vals = rng.standard_normal(M)
     R = synth.from_coo(M, N, rows, cols, vals)
-    prob = synth.Problem("single", R, K, 1e7, np.zeros(K), 2.0, float(K), np.eye(K), 1, 0,
+    prob = synth.Problem("single", R, K, 1e9, np.zeros(K), 2.0, float(K), np.eye(K), 1, 0,
                          (0.1 * rng.standard_normal((M, K))).astype(np.float32).astype(np.float64),
                          (0.1 * rng.standard_normal((N, K))).astype(np.float32).astype(np.float64),
                          np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), 0, 0.0)
