@@ -22,6 +22,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -31,6 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X = {"hbm_GBs": 8000.0, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0, "fp64_TFLOPs": 78.6}
+
+# HBM traffic of the row kernel, taken with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters and stored as text beside the sources it was measured on; it is
+# reported only while those sources are unchanged.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "rows_mixed_kernel_k64_bf16_movielens_hbm.txt")
+ROW_KERNEL_SOURCES = ("kernels_mixed.hip", "rowsolve.hpp", "rng.hpp", "common.hpp")
 
 
 def log(*a):
@@ -51,6 +58,33 @@ def rows_kernel_flops(row_counts, col_counts, K):
     return valu, mfma, rows, nnz
 
 
+def row_kernel_digest():
+    """sha256 over the sources the BF16 row kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ROW_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1705_10633_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """(HBM bytes per row-kernel launch, note) from the stored counter summary, or
+    (None, reason) when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None, "no counter summary"
+    fields = {}
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            m = re.match(r"^([a-z_0-9]+):\s*(\S+)", line)
+            if m:
+                fields[m.group(1)] = m.group(2)
+    if fields.get("kernel_sources_sha256") != row_kernel_digest():
+        return None, "row kernel changed since the counters were taken"
+    return float(fields["hbm_bytes_per_launch"]), "FETCH_SIZE x %s + WRITE_SIZE x %s, mean of both launches" % (
+        fields.get("fetch_scale", "?"), fields.get("write_scale", "?"))
+
+
 def time_sweeps(sampler, steps, warmup):
     import torch
     sampler.sweep(warmup)
@@ -66,30 +100,20 @@ def time_sweeps(sampler, steps, warmup):
     return start.elapsed_time(stop) / steps, wall / steps * 1e3
 
 
-def cpu_baseline(prob, frac=0.25, seed=0):
-    """The FP64 oracle on a random sample of the rows of both halves of one sweep."""
+def cpu_baseline(prob, n_sweeps=3, seed=2024):
+    """The FP64 oracle as it stands, running whole Gibbs sweeps of the same
+    workload on all host threads (row loops threaded, everything else serial)."""
     from oracle import oracle as O
-    rng = np.random.default_rng(seed)
     nth = os.cpu_count() or 1
-    R, K = prob.R, prob.K
-    Lam = np.eye(K) * 2.0
-    mu = np.zeros(K)
-    total_rows, total_t = 0, 0.0
-    for ptr, idx, val, other, n in ((R.row_ptr, R.col_idx, R.row_val, prob.V0, R.M),
-                                    (R.col_ptr, R.row_idx, R.col_val, prob.U0, R.N)):
-        pick = np.sort(rng.choice(n, size=max(1, int(frac * n)), replace=False))
-        cnt = ptr[pick + 1] - ptr[pick]
-        sp = np.zeros(pick.size + 1, np.int64)
-        np.cumsum(cnt, out=sp[1:])
-        sel = np.concatenate([np.arange(ptr[i], ptr[i + 1]) for i in pick]) if pick.size else np.zeros(0, np.int64)
-        Z = rng.standard_normal((pick.size, K))
-        t0 = time.perf_counter()
-        O.half_sweep(sp, idx[sel], val[sel], other, prob.alpha, prob.mean_rating, Lam, mu, Z, nthreads=nth)
-        total_t += time.perf_counter() - t0
-        total_rows += pick.size
-    return {"value": total_rows / total_t, "unit": "rows/s", "cores": nth, "kind": "oracle",
-            "sample": f"FP64 oracle row updates of a uniform {int(frac * 100)}% sample of the rows of both "
-                      f"halves of one sweep ({total_rows} rows, {total_t:.1f} s wall, {nth} threads)"}
+    tape = O.philox_tape(seed, 0, n_sweeps, prob.M, prob.N, prob.K, prob.nu0)
+    t0 = time.perf_counter()
+    O.gibbs(prob, tape, n_sweeps=n_sweeps, burnin=0, nthreads=nth)
+    t = time.perf_counter() - t0
+    rows = n_sweeps * (prob.M + prob.N)
+    return {"value": rows / t, "unit": "rows/s", "cores": nth, "kind": "oracle",
+            "sample": f"{n_sweeps} whole FP64 oracle sweeps of the full workload (both halves, both "
+                      f"Normal-Wishart steps and {prob.test_rows.size} held-out predictions per sweep): "
+                      f"{rows} rows in {t:.1f} s wall on {nth} threads"}
 
 
 def main():
@@ -160,14 +184,17 @@ def main():
     avg_launch_ms = t_rows / launches
     achieved = (valu / launches) / (avg_launch_ms * 1e-3) / 1e12
     mfma_achieved = (mfma / launches) / (avg_launch_ms * 1e-3) / 1e12
+    traffic, traffic_note = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved, "peak": MI355X["fp32_TFLOPs"], "unit": "TFLOP/s",
-                "frac": achieved / MI355X["fp32_TFLOPs"], "traffic": None}
+                "frac": achieved / MI355X["fp32_TFLOPs"], "traffic": traffic}
     detail = {"kernel": "rows_mixed_kernel<64,bf16>", "avg_launch_us": avg_launch_ms * 1e3,
               "valu_flop_per_sweep": valu, "mfma_bf16_flop_per_sweep": mfma,
               "mfma_bf16_achieved_TFLOPs": mfma_achieved,
               "mfma_bf16_frac": mfma_achieved / MI355X["bf16_TFLOPs"],
               "per_kernel_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in tm.items()},
-              "fallback_rows": info["fallback_rows"]}
+              "fallback_rows": info["fallback_rows"],
+              "traffic_note": traffic_note,
+              "hbm_GBs_at_traffic": (traffic / (avg_launch_ms * 1e-3) / 1e9) if traffic else None}
 
     fp64 = None
     if not args.no_fp64:

@@ -11,7 +11,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbpmf.so")
+LIB_PATH = os.environ.get("BPMF_LIBRARY") or os.path.join(HERE, "libbpmf.so")
 
 BPMF_FP64, BPMF_FP32, BPMF_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": BPMF_FP64, "fp32": BPMF_FP32, "bf16": BPMF_BF16}

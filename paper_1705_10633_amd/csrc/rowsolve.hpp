@@ -48,7 +48,10 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
 {
     using S = RowShape<KP>;
     const int lane = threadIdx.x & 63;
-    const int fb = lane % S::FB, rg = lane / S::FB;
+    // lanes 0..RG-1 stage feature block 0, lanes RG..2RG-1 block 1, ...: the
+    // 8-byte staging writes of a quarter-wave then spread over more banks
+    // than with consecutive lanes on consecutive feature blocks
+    const int fb = lane / S::RG, rg = lane % S::RG;
     // Software pipeline: the rows of chunk c+1 and the indices of chunk c+2
     // are in flight while chunk c is staged and multiplied.
     int jn[4], jnn[4];
@@ -205,6 +208,37 @@ __device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc,
     }
 }
 
+// A22 -= L21 L21^T for KP = 64, where lane 32 + r holds row r of L21 in
+// A[0..31] and row r of A22 in A[32..63].  The 32 x 32 x 32 product runs as
+// 16 rank-2 steps of v_mfma_f32_32x32x2_f32: the operand of step kk has
+// L21[:, 2kk] in lanes 0-31 and L21[:, 2kk + 1] in lanes 32-63, which one
+// permlane32 swap of A[2kk] and A[2kk + 1] produces.  Result register
+// 4j + i of lane l holds C[8j + 4(l / 32) + i][l % 32]; C is symmetric, so
+// lane 32 + r owns C[r][8j + 4 + i] and receives C[r][8j + i] from lane r by
+// a second swap.  Lanes 0-31 update entries right of their diagonal, which
+// are never read.
+__device__ __forceinline__ void syrk_trailing(float *A)
+{
+    floatx16 c = {};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[2 * kk]),
+                                                         __float_as_uint(A[2 * kk + 1]), false, false);
+        const float x = __uint_as_float(sw[1]);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(x, x, c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float own = c[4 * j + i];
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(own), __float_as_uint(own),
+                                                             false, false);
+            A[32 + 8 * j + 4 + i] -= own;
+            A[32 + 8 * j + i] -= __uint_as_float(sw[0]);
+        }
+}
+
 // Factor P (packed in `tri`) and return x = L^{-T}(L^{-1} b + z) on lane
 // ri = lane % KP, where lane ri holds b_ri and z_ri.  `fail` is set (uniformly
 // across the wave) when a pivot is not finite or not above
@@ -226,7 +260,10 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
     const int lane = threadIdx.x & 63;
     const int ri = lane % KP;
     float *invbuf = aux, *ybuf = aux + KP, *xbuf = aux + 2 * KP;
-    float *pbuf = tri;  // KP x 8 panel broadcast; P has been read into registers by then
+    float *pbuf = tri;  // KP x 12 panel broadcast; P has been read into registers by then
+    // pbuf rows are 12 floats apart, so 16 consecutive lanes cover all 64
+    // LDS banks with their 16-byte writes
+    constexpr int PS = 12;
     const int rbase = ri * (ri + 1) / 2;
     float A[KP];
 #pragma unroll
@@ -237,31 +274,33 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
     const float tau = 64.0f * (float)K * 0x1.0p-24f * dg;
     __syncthreads();
 
-    bool bad = false;
 #pragma unroll
     for (int c0 = 0; c0 < KP; c0 += PW) {
 #pragma unroll
         for (int k = c0; k < c0 + PW; ++k) {
-            float pkk = readlane_f(A[k], k);
-            const bool bk = !(pkk > tau) || !(pkk < 3.0e38f);
-            bad = bad || bk;
-            pkk = bk ? 1.0f : pkk;
-            const float inv = __builtin_amdgcn_rsqf(pkk);
+            // an unusable pivot gives a NaN, infinite or zero 1/sqrt and is
+            // caught by the check after the loop
+            const float inv = __builtin_amdgcn_rsqf(readlane_f(A[k], k));
             A[k] *= inv;
             invbuf[k] = inv;
 #pragma unroll
             for (int j = k + 1; j < c0 + PW; ++j) A[j] = fmaf(-A[k], readlane_f(A[k], j), A[j]);
         }
-        if (c0 + PW < KP) {
+        // With KP = 64 the panels of the first 32 columns update only columns
+        // below 32 here; their update of the trailing 32 x 32 block is one
+        // matrix-core product after the fourth panel (syrk_trailing).
+        constexpr int HALF = KP == 64 ? 32 : KP;
+        const int jend = c0 < HALF ? HALF : KP;
+        if (c0 + PW < jend) {
             if (lane < KP) {
-                *(float4 *)(pbuf + lane * PW) = make_float4(A[c0], A[c0 + 1], A[c0 + 2], A[c0 + 3]);
-                *(float4 *)(pbuf + lane * PW + 4) = make_float4(A[c0 + 4], A[c0 + 5], A[c0 + 6], A[c0 + 7]);
+                *(float4 *)(pbuf + lane * PS) = make_float4(A[c0], A[c0 + 1], A[c0 + 2], A[c0 + 3]);
+                *(float4 *)(pbuf + lane * PS + 4) = make_float4(A[c0 + 4], A[c0 + 5], A[c0 + 6], A[c0 + 7]);
             }
             __syncthreads();
 #pragma unroll
-            for (int j = c0 + PW; j < KP; ++j) {
-                const float4 p0 = *(const float4 *)(pbuf + j * PW);
-                const float4 p1 = *(const float4 *)(pbuf + j * PW + 4);
+            for (int j = c0 + PW; j < jend; ++j) {
+                const float4 p0 = *(const float4 *)(pbuf + j * PS);
+                const float4 p1 = *(const float4 *)(pbuf + j * PS + 4);
                 float t = A[j];
                 t = fmaf(-A[c0 + 0], p0.x, t);
                 t = fmaf(-A[c0 + 1], p0.y, t);
@@ -275,8 +314,17 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
             }
             __syncthreads();
         }
+        if constexpr (KP == 64)
+            if (c0 + PW == HALF) syrk_trailing(A);
     }
-    fail = bad;
+    {
+        // pivot d_k fails when it is not finite or d_k <= tau, i.e. when
+        // 1/sqrt(d_k) is not a positive finite number with tau / d_k < 1;
+        // the identity pivots of the padding are not checked
+        const float ik = invbuf[ri];
+        const bool bk = (ri < K) && !((ik > 0.0f) && (ik * ik * tau < 1.0f));
+        fail = __ballot(bk) != 0;
+    }
     const float invd = invbuf[ri];
     // y = L^{-1} b: y_k is taken from lane k before later steps overwrite it
 #pragma unroll
@@ -285,7 +333,8 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
         ybuf[k] = yk;
         bb = fmaf(-A[k], yk, bb);
     }
-    // rows of L back to LDS for the transposed solve
+    // rows of L back to LDS for the transposed solve (lower triangle only:
+    // a lane's entries right of its diagonal would land in other rows' slots)
     if (lane < KP) {
 #pragma unroll
         for (int c = 0; c < KP; ++c)
