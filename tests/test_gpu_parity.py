@@ -73,12 +73,18 @@ def test_fp64_device_generator_parity():
     prob = synth.uniform_planted(M=300, N=200, nnz=6000, seed=11, n_sweeps=3, burnin=0)
     seed = 0x1234ABCD5678
     tape = O.philox_tape(seed, 0, 3, prob.M, prob.N, prob.K, prob.nu0)
-    ref = O.gibbs(prob, tape, nthreads=8)
+    ref = O.gibbs(prob, tape, nthreads=8, want_hyper=True)
     s = _run_gpu(prob, None, 3, seed=seed)
     eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
     ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
     print(f"philox max row err U {eu.max():.3e} V {ev.max():.3e}")
     assert eu.max() <= FP64_TOL and ev.max() <= FP64_TOL
+    # the users' hyper step runs one sweep ahead with device draws; the
+    # reported hyper-parameters are still those of the last sweep
+    h = s.hyper()
+    for k in ("Lambda_U", "mu_U", "Lambda_V", "mu_V"):
+        a, b = h[k], ref["hyper"][k]
+        assert np.max(np.abs(a - b)) <= FP64_TOL * max(1.0, np.max(np.abs(b))), k
 
 
 @pytest.mark.parametrize("K,M,N,nnz", [(1, 40, 30, 300), (3, 50, 41, 200), (33, 70, 65, 900),
