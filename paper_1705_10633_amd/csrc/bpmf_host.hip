@@ -66,7 +66,7 @@ struct WsLayout {
 };
 
 struct Offsets {
-    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], mu0, w0inv,
+    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], mu0, w0inv,
         order[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
@@ -94,9 +94,11 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
         o.lmu[s] = w.add(sizeof(double) * K);
         o.lamf[s] = w.add(sizeof(float) * K * K);
         o.lmuf[s] = w.add(sizeof(float) * K);
+        o.lamt[s] = w.add(sizeof(float) * (size_t)padded_k(K) * (padded_k(K) + 3) / 2);
         o.order[s] = w.add(sizeof(int32_t) * n[s]);
         o.fblist[s] = w.add(mk ? sizeof(int32_t) * n[s] : 0);
-        o.shadow[s] = w.add((mk && p->precision == BPMF_BF16) ? sizeof(uint16_t) * n[s] * padded_k(K) : 0);
+        // BF16 copy plus one all-zero row (the gather target past a row's end)
+        o.shadow[s] = w.add((mk && p->precision == BPMF_BF16) ? sizeof(uint16_t) * (n[s] + 1) * padded_k(K) : 0);
         o.valsf[s] = w.add((mixed && R->val_is_f64) ? sizeof(float) * R->nnz : 0);
     }
     o.mu0 = w.add(sizeof(double) * K);
@@ -341,6 +343,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         c->hyp[sd].Lmu = c->at<double>(off.lmu[sd]);
         c->hyp[sd].Lambda_f = c->at<float>(off.lamf[sd]);
         c->hyp[sd].Lmu_f = c->at<float>(off.lmuf[sd]);
+        c->hyp[sd].Lambda_tri = c->at<float>(off.lamt[sd]);
     }
     auto bail = [&](bpmf_status e) { delete c; return e; };
 #define HIP_OK_C(expr)                                                                      \
@@ -504,6 +507,7 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
     const bool mixed_kernel = !f64 && mixed_supported(K);
     SideArgs a;
     a.n_rows = n;
+    a.n_other = side == 0 ? R.N : R.M;
     a.ptr = side == 0 ? R.d_row_ptr : R.d_col_ptr;
     a.idx = side == 0 ? R.d_col_idx : R.d_row_idx;
     const void *vals_orig = side == 0 ? R.d_row_val : R.d_col_val;
@@ -729,6 +733,7 @@ static bpmf_status state_copy(bpmf_ctx *c, char *h, bool save, hipStream_t s)
         for (int sd = 0; sd < 2; ++sd) {
             HIP_OK(launch_f64_to_f32(c->hyp[sd].Lambda, c->hyp[sd].Lambda_f, (int64_t)K * K, s));
             HIP_OK(launch_f64_to_f32(c->hyp[sd].Lmu, c->hyp[sd].Lmu_f, K, s));
+            HIP_OK(launch_lambda_tri(c->hyp[sd], K, c->KP, s));
         }
         if (c->precision == BPMF_BF16 && mixed_supported(K)) {
             HIP_OK(launch_to_bf16((const float *)c->dU, c->R.M, K, c->KP, c->at<uint16_t>(c->off.shadow[0]), s));

@@ -43,11 +43,15 @@ struct HyperDev {
     double *Lmu;     // K  (Lambda mu)
     float *Lambda_f; // K x K
     float *Lmu_f;    // K
+    // FP32 Lambda as the mixed row kernel's packed lower triangle of the
+    // padded size KP (row r at r (r + 1) / 2, identity in the padding), KP (KP + 3) / 2 floats
+    float *Lambda_tri;
 };
 
 // One half-sweep: rows of one side against the other side's factors.
 struct SideArgs {
     int64_t n_rows;
+    int64_t n_other;        // rows of the other side (its BF16 copy has one more, all zeros)
     const int64_t *ptr;
     const int32_t *idx;
     const void *val;        // float or double ratings
@@ -98,6 +102,7 @@ hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, dou
                           int64_t n, const int32_t *rows, const int32_t *cols, double *out,
                           double *accum, const DevState *state, int burnin, hipStream_t s);
 hipError_t launch_advance_burnin(DevState *state, int burnin, hipStream_t s);
+hipError_t launch_lambda_tri(HyperDev hyp, int K, int KP, hipStream_t s);
 hipError_t launch_reset_fallback(DevState *state, int side, hipStream_t s);
 hipError_t launch_to_bf16(const float *X, int64_t n, int K, int stride, uint16_t *out,
                           hipStream_t s);

@@ -47,17 +47,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     float bacc = 0.0f;
 
     if constexpr (BF16)
-        gram_bf16<KP>(a.idx + s0, vals + s0, s1 - s0, a.other_bf16, a.shadow_stride, rbar,
-                      (char *)u, rv, acc, bacc);
+        gram_bf16<KP>(a.idx + s0, vals + s0, s1 - s0, a.other_bf16, a.shadow_stride, (int32_t)a.n_other,
+                      rbar, (char *)u, (uint32_t *)rv, acc, bacc);
     else
         gram_f32<KP>(a.idx + s0, vals + s0, s1 - s0, (const float *)a.other, K, rbar, u, rv,
                      sidx, acc, bacc);
 
     float *tri = u;
-    const float *Lf = hyp.Lambda_f;
-    store_precision<KP>(tri, acc, K, alpha, [=](int r, int c) { return Lf[r * K + c]; });
+    store_precision_tri<KP>(tri, acc, alpha, hyp.Lambda_tri);
     const int ri = lane % KP;
-    const float bb = (ri < K) ? fmaf(alpha, bacc, hyp.Lmu_f[ri]) : 0.0f;
+    const float lmu = hyp.Lmu_f[ri < K ? ri : 0];
+    const float bb = (ri < K) ? fmaf(alpha, bacc, lmu) : 0.0f;
 
     float z;
     if (draws.tape_rows) {

@@ -398,6 +398,8 @@ __global__ __launch_bounds__(256) void nw_wave_kernel(const double *sums, int64_
         const int a = lane;
         double *lrow = hyp.Lambda + (size_t)(a < K ? a : 0) * K;
         float *lfrow = hyp.Lambda_f + (size_t)(a < K ? a : 0) * K;
+        const int KPm = K <= 32 ? 32 : 64;  // padded size of the mixed row kernel
+        float *trow = hyp.Lambda_tri + (a < KPm ? a * (a + 1) / 2 : 0);
         double lmu = 0.0;
 #pragma unroll
         for (int cb = 0; cb < NWK; cb += 16) {
@@ -428,6 +430,8 @@ __global__ __launch_bounds__(256) void nw_wave_kernel(const double *sums, int64_
                     lrow[c] = acc[cc];
                     lfrow[c] = (float)acc[cc];
                 }
+                if (c <= a && a < KPm)
+                    trow[c] = (a < K && c < K) ? (float)acc[cc] : (a == c ? 1.0f : 0.0f);
                 lmu = fma(acc[cc], mul[c], lmu);
             }
             // pin the running sum here, so the block's 16 entries die now
@@ -441,7 +445,24 @@ __global__ __launch_bounds__(256) void nw_wave_kernel(const double *sums, int64_
     if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
 }
 
+// Lambda_tri from Lambda_f (after a state restore).
+__global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, int KP)
+{
+    for (int t = threadIdx.x; t < KP * KP; t += blockDim.x) {
+        const int r = t / KP, c = t - r * KP;
+        if (c <= r)
+            hyp.Lambda_tri[r * (r + 1) / 2 + c] = (r < K && c < K) ? hyp.Lambda_f[r * K + c] : (r == c ? 1.0f : 0.0f);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_lambda_tri(HyperDev hyp, int K, int KP, hipStream_t s)
+{
+    if (K > 64) return hipSuccess;
+    hipLaunchKernelGGL(lambda_tri_kernel, dim3(1), dim3(256), 0, s, hyp, K, KP);
+    return hipGetLastError();
+}
 
 size_t nw_scratch_doubles(int K)
 {

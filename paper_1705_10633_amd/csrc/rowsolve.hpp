@@ -1,7 +1,7 @@
 // rowsolve.hpp -- wavefront-level building blocks of the mixed-precision row
 // update (one 64-lane wavefront per row, KP = 32 or 64 padded latent size):
-//   gram_bf16 / gram_f32 : G = sum_j v_j v_j^T (lower 32x32 tiles) and
-//                          sum_j (r_j - rbar) v_j on the matrix cores;
+//   gram_bf16 / gram_f32 : G = sum_j v_j v_j^T (lower 32x32 tiles) on the
+//                          matrix cores and sum_j (r_j - rbar) v_j;
 //   store_precision      : P = Lambda + alpha G into a packed lower triangle
 //                          (padding rows/columns get the identity);
 //   chol_solve           : x = L^{-T}(L^{-1} b + z) with L L^T = P, FP32,
@@ -14,6 +14,7 @@
 namespace bpmf {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 template <int KP>
@@ -38,13 +39,19 @@ __device__ __forceinline__ float readlane_f(float v, int lane)
 }
 
 // BF16 gathers: rows `idx[0..nnz)` of `src` (BF16, row stride `stride`,
-// 16-byte aligned rows) with ratings `vals` (FP32).  The chunk is staged
-// feature-major so each lane's matrix-core operand (8 consecutive nnz of one
-// feature) is one 16-byte LDS read.
+// 16-byte aligned rows) with ratings `vals` (FP32).  Row `sentinel` of `src`
+// is all zeros; positions past nnz gather it, so no load needs a lane mask.
+// The chunk is staged feature-major so each lane's matrix-core operand (8
+// consecutive nnz of one feature) is one 16-byte LDS read.
+//
+// The right-hand side sum_j r'_j v_j runs on v_dot2c_f32_bf16 over pairs of
+// ratings, with r' = r - rbar split into two BF16 parts hi = bf16(r') and
+// lo = bf16(r' - hi), so r' is carried to about 2^-17 relative; `rvp` holds
+// CH / 2 packed hi pairs followed by CH / 2 lo pairs.
 template <int KP>
 __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals, int64_t nnz,
-                                          const uint16_t *src, int stride, float rbar, char *stage,
-                                          float *rv, floatx16 *acc, float &bacc)
+                                          const uint16_t *src, int stride, int32_t sentinel, float rbar,
+                                          char *stage, uint32_t *rvp, floatx16 *acc, float &bacc)
 {
     using S = RowShape<KP>;
     const int lane = threadIdx.x & 63;
@@ -52,48 +59,34 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
     // 8-byte staging writes of a quarter-wave then spread over more banks
     // than with consecutive lanes on consecutive feature blocks
     const int fb = lane / S::RG, rg = lane % S::RG;
-    // Software pipeline: the rows of chunk c+1 and the indices of chunk c+2
-    // are in flight while chunk c is staged and multiplied.
-    int jn[4], jnn[4];
-    float vn[4];
-    uint4 dn[4];
     auto load_idx = [&](int64_t c0, int *j) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t n = c0 + rg * 4 + q;
-            j[q] = n < nnz ? idx[n] : -1;
+            const int jj = idx[n < nnz ? n : nnz - 1];
+            j[q] = n < nnz ? jj : sentinel;
         }
     };
     auto load_rows = [&](int64_t c0, const int *j, uint4 *d, float *v) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            d[q] = j[q] >= 0 ? *(const uint4 *)(src + (int64_t)j[q] * stride + fb * 8)
-                             : make_uint4(0u, 0u, 0u, 0u);
+            d[q] = *(const uint4 *)(src + (int64_t)j[q] * stride + fb * 8);
             const int64_t n = c0 + rg * 4 + q;
-            v[q] = (fb == 0 && n < nnz) ? vals[n] - rbar : 0.0f;
+            const float r = vals[n < nnz ? n : nnz - 1];
+            v[q] = n < nnz ? r - rbar : 0.0f;
         }
     };
-    if (nnz > 0) {
-        load_idx(0, jn);
-        load_rows(0, jn, dn, vn);
-        load_idx(S::CH, jnn);
-    }
-    for (int64_t c0 = 0; c0 < nnz; c0 += S::CH) {
-        uint4 d[4];
-        float v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            d[q] = dn[q];
-            v[q] = vn[q];
-            jn[q] = jnn[q];
-        }
-        if (c0 + S::CH < nnz) {
-            load_rows(c0 + S::CH, jn, dn, vn);
-            load_idx(c0 + 2 * S::CH, jnn);
-        }
+    // r' halves and the feature-major copy of one chunk into LDS
+    auto stage_chunk = [&](const uint4 *d, const float *v) {
         if (fb == 0) {
+            uint32_t hi[4], lo[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rv[rg * 4 + q] = v[q];
+            for (int q = 0; q < 4; ++q) {
+                hi[q] = f32_to_bf16_rne(v[q]);
+                lo[q] = f32_to_bf16_rne(v[q] - bf16_to_f32((uint16_t)hi[q]));
+            }
+            *(uint2 *)(rvp + rg * 2) = make_uint2(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16));
+            *(uint2 *)(rvp + S::CH / 2 + rg * 2) = make_uint2(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16));
         }
         const uint32_t w0[4] = {d[0].x, d[0].y, d[0].z, d[0].w};
         const uint32_t w1[4] = {d[1].x, d[1].y, d[1].z, d[1].w};
@@ -110,7 +103,9 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
             *(uint2 *)(stage + f * S::SB + rg * 8) = lo;
             *(uint2 *)(stage + (f + 1) * S::SB + rg * 8) = hi;
         }
-        __syncthreads();
+    };
+    // Gram tiles and right-hand side of the staged chunk
+    auto multiply_chunk = [&]() {
 #pragma unroll
         for (int ks = 0; ks < S::CH / 16; ++ks) {
             const int off = (ks * 16 + (lane >> 5) * 8) * 2;
@@ -122,14 +117,42 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
                 acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, acc[2], 0, 0, 0);
             }
         }
-        {
-            constexpr int SPLIT = 64 / KP;
-            constexpr int PER = S::CH / SPLIT;
-            const int f = lane % KP, part = lane / KP;
-            const uint16_t *sp = (const uint16_t *)(stage + f * S::SB) + part * PER;
-#pragma unroll 8
-            for (int n = 0; n < PER; ++n) bacc = fmaf(bf16_to_f32(sp[n]), rv[part * PER + n], bacc);
+        constexpr int SPLIT = 64 / KP;
+        constexpr int PAIRS = S::CH / SPLIT / 2;
+        const int f = lane % KP, part = lane / KP;
+        const uint32_t *sp = (const uint32_t *)(stage + f * S::SB) + part * PAIRS;
+        const uint32_t *hp = rvp + part * PAIRS, *lp = rvp + S::CH / 2 + part * PAIRS;
+#pragma unroll
+        for (int p = 0; p < PAIRS; ++p) {
+            bf16x2_t x, yh, yl;
+            const uint32_t sv = sp[p], hv = hp[p], lv = lp[p];
+            __builtin_memcpy(&x, &sv, 4);
+            __builtin_memcpy(&yh, &hv, 4);
+            __builtin_memcpy(&yl, &lv, 4);
+            bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yh, bacc, false);
+            bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yl, bacc, false);
         }
+    };
+    // Software pipeline with one register set: as soon as a chunk is staged,
+    // the rows of the next chunk (whose indices are already loaded) and the
+    // indices of the one after are requested, and they arrive while the
+    // staged chunk is multiplied.
+    int j[4];
+    uint4 d[4];
+    float v[4];
+    if (nnz > 0) {
+        load_idx(0, j);
+        load_rows(0, j, d, v);
+        if (S::CH < nnz) load_idx(S::CH, j);
+    }
+    for (int64_t c0 = 0; c0 < nnz; c0 += S::CH) {
+        stage_chunk(d, v);
+        if (c0 + S::CH < nnz) {
+            load_rows(c0 + S::CH, j, d, v);
+            if (c0 + 2 * S::CH < nnz) load_idx(c0 + 2 * S::CH, j);
+        }
+        __syncthreads();
+        multiply_chunk();
         __syncthreads();
     }
     if constexpr (KP == 32) bacc += __shfl_xor(bacc, 32);
@@ -182,7 +205,8 @@ __device__ __forceinline__ void gram_f32(const int32_t *idx, const float *vals, 
 }
 
 // P = Lambda + alpha G into the packed lower triangle `tri` (row r starts at
-// r(r+1)/2).  lam(r, c) returns Lambda_rc for r, c < K.
+// r(r+1)/2).  lam(r, c) returns Lambda_rc for r, c < K; it is evaluated for
+// every entry (with clamped indices) so the loads are issued together.
 template <int KP, typename LamFn>
 __device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc, int K, float alpha,
                                                 LamFn lam)
@@ -198,12 +222,35 @@ __device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc,
             for (int i = 0; i < 4; ++i) {
                 const int r = 32 * ta + 8 * j + 4 * (lane >> 5) + i;
                 const int c = 32 * tb + (lane & 31);
-                if (c <= r) {
-                    float v;
-                    if (r < K && c < K) v = fmaf(alpha, acc[t][4 * j + i], lam(r, c));
-                    else v = (r == c) ? 1.0f : 0.0f;
-                    tri[r * (r + 1) / 2 + c] = v;
-                }
+                const bool in = r < K && c < K;
+                const float l = lam(in ? r : 0, in ? c : 0);
+                const float v = in ? fmaf(alpha, acc[t][4 * j + i], l) : ((r == c) ? 1.0f : 0.0f);
+                if (c <= r) tri[r * (r + 1) / 2 + c] = v;
+            }
+    }
+}
+
+// The same from Lambda stored as the padded packed triangle `lamtri` (the
+// padding entries of the Gram are zero): no index checks, and every load and
+// store uses the same offset.
+template <int KP>
+__device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *acc, float alpha,
+                                                    const float *lamtri)
+{
+    using S = RowShape<KP>;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t < S::NTILE; ++t) {
+        const int ta = (t == 0) ? 0 : 1, tb = (t == 2) ? 1 : 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 32 * ta + 8 * j + 4 * (lane >> 5) + i;
+                const int c = 32 * tb + (lane & 31);
+                const int e = r * (r + 1) / 2 + c;  // < KP (KP + 3) / 2 for every lane
+                const float v = fmaf(alpha, acc[t][4 * j + i], lamtri[e]);
+                if (c <= r) tri[e] = v;
             }
     }
 }
