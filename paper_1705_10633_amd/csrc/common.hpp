@@ -64,6 +64,15 @@ struct SideArgs {
     const int32_t *order;   // rows in processing order (nnz descending)
 };
 
+// Masked loads are written as an unconditional load (from a clamped, valid
+// index) scaled or blended by the mask, so the compiler does not put each
+// load behind its own branch (which also waits for every load in flight).
+__device__ __forceinline__ int blend_idx(bool ok, int v, int other)
+{
+    const int m = -(int)ok;
+    return (v & m) | (other & ~m);
+}
+
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 {
     uint32_t u = __float_as_uint(f);

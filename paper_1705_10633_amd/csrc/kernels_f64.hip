@@ -82,13 +82,15 @@ __global__ __launch_bounds__(256) void rows_f64_kernel(SideArgs a, int K, double
         for (int64_t c0 = s0; c0 < s1; c0 += F64_CH) {
             const int cnt = (int)min((int64_t)F64_CH, s1 - c0);
             if (tid < F64_CH) {
-                s_idx[tid] = tid < cnt ? a.idx[c0 + tid] : 0;
-                rv[tid] = tid < cnt ? ld<VT>(a.val, c0 + tid) - rbar : 0.0;
+                // clamped indices: every load is valid, so they are not masked
+                const int tc = tid < cnt ? tid : cnt - 1;
+                s_idx[tid] = blend_idx(tid < cnt, a.idx[c0 + tc], 0);
+                rv[tid] = (ld<VT>(a.val, c0 + tc) - rbar) * (tid < cnt ? 1.0 : 0.0);
             }
             __syncthreads();
             for (int e = tid; e < F64_CH * KS; e += 256) {
                 int n = e / KS, f = e - n * KS;
-                stage[e] = (n < cnt && f < K) ? (double)other[(int64_t)s_idx[n] * K + f] : 0.0;
+                stage[e] = (double)other[(int64_t)s_idx[n] * K + (f < K ? f : K - 1)] * ((n < cnt && f < K) ? 1.0 : 0.0);
             }
             __syncthreads();
 #pragma unroll
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(256) void stats_kernel(const XT *X, int64_t n, int 
         const int cnt = (int)min((int64_t)32, r1 - c0);
         for (int e = tid; e < 32 * KS; e += 256) {
             int q = e / KS, f = e - q * KS;
-            stage[e] = (q < cnt && f < K) ? (double)X[(c0 + q) * K + f] : 0.0;
+            stage[e] = (double)X[(c0 + (q < cnt ? q : cnt - 1)) * K + (f < K ? f : K - 1)] * ((q < cnt && f < K) ? 1.0 : 0.0);
         }
         __syncthreads();
 #pragma unroll
@@ -295,7 +297,9 @@ __global__ __launch_bounds__(256) void stats_mfma_kernel(const XT *X, int64_t n,
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int f = 16 * b + i16;
-                x[u][b] = (r < r1 && f < K) ? (double)X[r * K + f] : 0.0;
+                // clamped indices (r1 > r0 here): the loads carry no lane masks
+                // and are issued together
+                x[u][b] = (double)X[(r < r1 ? r : r1 - 1) * K + (f < K ? f : K - 1)] * ((r < r1 && f < K) ? 1.0 : 0.0);
             }
         }
 #pragma unroll

@@ -59,31 +59,34 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
     // 8-byte staging writes of a quarter-wave then spread over more banks
     // than with consecutive lanes on consecutive feature blocks
     const int fb = lane / S::RG, rg = lane % S::RG;
+    // Loaded values stay raw until they are used (a chunk later), so no
+    // arithmetic right after a load forces a wait for the loads in flight.
     auto load_idx = [&](int64_t c0, int *j) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t n = c0 + rg * 4 + q;
-            const int jj = idx[n < nnz ? n : nnz - 1];
-            j[q] = n < nnz ? jj : sentinel;
+            j[q] = idx[n < nnz ? n : nnz - 1];
         }
     };
     auto load_rows = [&](int64_t c0, const int *j, uint4 *d, float *v) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            d[q] = *(const uint4 *)(src + (int64_t)j[q] * stride + fb * 8);
             const int64_t n = c0 + rg * 4 + q;
-            const float r = vals[n < nnz ? n : nnz - 1];
-            v[q] = n < nnz ? r - rbar : 0.0f;
+            const int jj = blend_idx(n < nnz, j[q], sentinel);
+            d[q] = *(const uint4 *)(src + (int64_t)jj * stride + fb * 8);
+            v[q] = vals[n < nnz ? n : nnz - 1];
         }
     };
     // r' halves and the feature-major copy of one chunk into LDS
-    auto stage_chunk = [&](const uint4 *d, const float *v) {
+    auto stage_chunk = [&](int64_t c0, const uint4 *d, const float *vraw) {
         if (fb == 0) {
             uint32_t hi[4], lo[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                hi[q] = f32_to_bf16_rne(v[q]);
-                lo[q] = f32_to_bf16_rne(v[q] - bf16_to_f32((uint16_t)hi[q]));
+                const int64_t n = c0 + rg * 4 + q;
+                const float v = (vraw[q] - rbar) * (n < nnz ? 1.0f : 0.0f);
+                hi[q] = f32_to_bf16_rne(v);
+                lo[q] = f32_to_bf16_rne(v - bf16_to_f32((uint16_t)hi[q]));
             }
             *(uint2 *)(rvp + rg * 2) = make_uint2(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16));
             *(uint2 *)(rvp + S::CH / 2 + rg * 2) = make_uint2(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16));
@@ -146,7 +149,7 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
         if (S::CH < nnz) load_idx(S::CH, j);
     }
     for (int64_t c0 = 0; c0 < nnz; c0 += S::CH) {
-        stage_chunk(d, v);
+        stage_chunk(c0, d, v);
         if (c0 + S::CH < nnz) {
             load_rows(c0 + S::CH, j, d, v);
             if (c0 + 2 * S::CH < nnz) load_idx(c0 + 2 * S::CH, j);
@@ -169,15 +172,16 @@ __device__ __forceinline__ void gram_f32(const int32_t *idx, const float *vals, 
     for (int64_t c0 = 0; c0 < nnz; c0 += S::CHF) {
         const int cnt = (int)min((int64_t)S::CHF, nnz - c0);
         if (lane < S::CHF) {
-            sidx[lane] = lane < cnt ? idx[c0 + lane] : 0;
-            rv[lane] = lane < cnt ? vals[c0 + lane] - rbar : 0.0f;
+            const int lc = lane < cnt ? lane : cnt - 1;  // clamped: unmasked loads
+            sidx[lane] = blend_idx(lane < cnt, idx[c0 + lc], 0);
+            rv[lane] = (vals[c0 + lc] - rbar) * (lane < cnt ? 1.0f : 0.0f);
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < S::CHF * KP / 64; ++t) {
             const int e = lane + 64 * t;
             const int n = e / KP, f = e % KP;
-            stage[n * S::KSF + f] = (n < cnt && f < K) ? src[(int64_t)sidx[n] * K + f] : 0.0f;
+            stage[n * S::KSF + f] = src[(int64_t)sidx[n] * K + (f < K ? f : K - 1)] * ((n < cnt && f < K) ? 1.0f : 0.0f);
         }
         __syncthreads();
 #pragma unroll
