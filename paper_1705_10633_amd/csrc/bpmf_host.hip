@@ -31,7 +31,6 @@ hipError_t launch_sum_values(const void *vals, int is_f64, int64_t n, double *pa
 hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_t n,
                                 const DevState *state, double *out, hipStream_t s);
 hipError_t prepare_rows_f64(int K);
-hipError_t prepare_nw(int K);
 }  // namespace bpmf
 
 using namespace bpmf;
@@ -128,8 +127,6 @@ struct bpmf_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
-    hipStream_t aux = nullptr;  // second stream for the overlapped hyper step
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool broken = false;
     // per-kernel timing
     bool timing = false;
@@ -352,11 +349,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         if (_e != hipSuccess) return bail(fail(BPMF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e))); \
     } while (0)
 
-    HIP_OK_C(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-    HIP_OK_C(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-    HIP_OK_C(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIP_OK_C(prepare_rows_f64(K));
-    HIP_OK_C(prepare_nw(K));
     HIP_OK_C(launch_fill_zero(c->ws, off.total - kAlign, s));
 
     // mean rating
@@ -478,21 +471,37 @@ static DrawSrc draws_for(bpmf_ctx *c, int side, const double *tape_block)
     return d;
 }
 
-// Hyper-parameters of one side from that side's current factors (stream s).
-static bpmf_status enqueue_hyper(bpmf_ctx *c, int side, const DrawSrc &d, hipStream_t s)
+// Hyper-parameters of both sides from their current factors (stream s):
+// the statistics of U and V in one launch, one reduction, and one launch
+// with a workgroup per side for the Normal-Wishart draws.
+static bpmf_status enqueue_hyper(bpmf_ctx *c, const DrawSrc &d0, const DrawSrc &d1, hipStream_t s)
 {
     const int K = c->K;
-    const int64_t n = side == 0 ? c->R.M : c->R.N;
-    void *X = side == 0 ? c->dU : c->dV;
+    StatsSides ss;
+    ss.X[0] = c->dU;
+    ss.X[1] = c->dV;
+    ss.n[0] = c->R.M;
+    ss.n[1] = c->R.N;
+    for (int sd = 0; sd < 2; ++sd) {
+        ss.partials[sd] = c->at<double>(c->off.partials[sd]);
+        ss.n_chunks[sd] = c->n_chunks[sd];
+    }
+    double *const sums[2] = {c->at<double>(c->off.sums[0]), c->at<double>(c->off.sums[1])};
     hipEvent_t t0 = time_begin(c, s);
-    HIP_OK(launch_stats(X, c->x_f64() ? 1 : 0, n, K, c->at<double>(c->off.partials[side]), c->n_chunks[side], s));
-    HIP_OK(launch_stats_reduce(c->at<double>(c->off.partials[side]), c->n_chunks[side], K,
-                               c->at<double>(c->off.sums[side]), s));
+    HIP_OK(launch_stats(ss, c->x_f64() ? 1 : 0, K, s));
+    HIP_OK(launch_stats_reduce(ss, sums, K, s));
     time_end(c, 0, t0, s);
+    NwSide nw[2];
+    const DrawSrc *d[2] = {&d0, &d1};
+    for (int sd = 0; sd < 2; ++sd) {
+        nw[sd].sums = sums[sd];
+        nw[sd].n = ss.n[sd];
+        nw[sd].draws = *d[sd];
+        nw[sd].scratch = c->at<double>(c->off.scratch[sd]);
+        nw[sd].hyp = c->hyp[sd];
+    }
     t0 = time_begin(c, s);
-    HIP_OK(launch_nw(c->at<double>(c->off.sums[side]), n, K, c->at<double>(c->off.mu0), c->beta0, c->nu0,
-                     c->at<double>(c->off.w0inv), d, c->at<double>(c->off.scratch[side]), c->hyp[side],
-                     K <= 64 ? 1 : 0, c->state, s));
+    HIP_OK(launch_nw(nw, K, c->at<double>(c->off.mu0), c->beta0, c->nu0, c->at<double>(c->off.w0inv), c->state, s));
     time_end(c, 1, t0, s);
     return BPMF_OK;
 }
@@ -538,7 +547,6 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
         time_end(c, 2 + side, t0, s);
         return BPMF_OK;
     }
-    HIP_OK(launch_reset_fallback(c->state, side, s));
     t0 = time_begin(c, s);
     HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d,
                              c->at<int32_t>(c->off.fblist[side]), c->state, s));
@@ -550,25 +558,19 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
     return BPMF_OK;
 }
 
-// One sweep.  The movies' hyper-parameters depend only on V, which the
-// users' half does not change, so they are computed on the auxiliary stream
-// while the users' rows are updated; the movies' rows wait for both.
+// One sweep, in Algorithm 1's order with users first: the hyper-parameters
+// of both sides (each from its own factors, so they are computed together),
+// the users' rows, the movies' rows, the held-out predictions.
 static bpmf_status enqueue_sweep(bpmf_ctx *c, const double *tape, hipStream_t s)
 {
     const int K = c->K;
     const int64_t hb = (int64_t)K + (int64_t)K * (K - 1) / 2 + K;
     const DrawSrc d0 = draws_for(c, 0, tape);
     const DrawSrc d1 = draws_for(c, 1, tape ? tape + hb + c->R.M * K : nullptr);
-    HIP_OK(hipEventRecord(c->ev_fork, s));
-    HIP_OK(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-    bpmf_status st = enqueue_hyper(c, 1, d1, c->aux);
-    if (st != BPMF_OK) return st;
-    HIP_OK(hipEventRecord(c->ev_join, c->aux));
-    st = enqueue_hyper(c, 0, d0, s);
+    bpmf_status st = enqueue_hyper(c, d0, d1, s);
     if (st != BPMF_OK) return st;
     st = enqueue_rows(c, 0, d0, s);
     if (st != BPMF_OK) return st;
-    HIP_OK(hipStreamWaitEvent(s, c->ev_join, 0));
     st = enqueue_rows(c, 1, d1, s);
     if (st != BPMF_OK) return st;
     if (c->n_test > 0) {
@@ -801,9 +803,6 @@ bpmf_status bpmf_destroy(bpmf_ctx *c)
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->graph) hipGraphDestroy(c->graph);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-    if (c->aux) hipStreamDestroy(c->aux);
-    if (c->ev_fork) hipEventDestroy(c->ev_fork);
-    if (c->ev_join) hipEventDestroy(c->ev_join);
     delete c;
     return BPMF_OK;
 }

@@ -91,15 +91,26 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h)
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files; all return hipError_t of the launch)
 // ---------------------------------------------------------------------------
-hipError_t launch_stats(const void *X, int x_is_f64, int64_t n, int K, double *partials,
-                        int n_chunks, hipStream_t s);
+// Both sides of a sweep's hyper-parameter step (0 users, 1 movies).
+struct StatsSides {
+    const void *X[2];      // factor matrices (FP64 or FP32)
+    int64_t n[2];          // rows
+    double *partials[2];   // per-chunk partial sums
+    int n_chunks[2];
+};
+struct NwSide {
+    const double *sums;    // sum x (K) then sum x x^T (packed lower, K(K+1)/2)
+    int64_t n;
+    DrawSrc draws;
+    double *scratch;       // K > 64 only
+    HyperDev hyp;
+};
+hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s);
 int stats_chunks(int64_t n);
 size_t nw_scratch_doubles(int K);
-hipError_t launch_stats_reduce(const double *partials, int n_chunks, int K, double *sums,
-                               hipStream_t s);
-hipError_t launch_nw(const double *sums, int64_t n, int K, const double *mu0, double beta0,
-                     double nu0, const double *W0inv, DrawSrc draws, double *scratch,
-                     HyperDev hyp, int use_lds, DevState *state, hipStream_t s);
+hipError_t launch_stats_reduce(const StatsSides &ss, double *const sums[2], int K, hipStream_t s);
+hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double beta0, double nu0,
+                     const double *W0inv, DevState *state, hipStream_t s);
 hipError_t launch_rows_f64(const SideArgs &a, int K, double alpha, double rbar,
                            HyperDev hyp, DrawSrc draws, const int32_t *list,
                            const int32_t *list_count, int64_t max_rows, int x_is_f32,
@@ -112,7 +123,6 @@ hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, dou
                           double *accum, const DevState *state, int burnin, hipStream_t s);
 hipError_t launch_advance_burnin(DevState *state, int burnin, hipStream_t s);
 hipError_t launch_lambda_tri(HyperDev hyp, int K, int KP, hipStream_t s);
-hipError_t launch_reset_fallback(DevState *state, int side, hipStream_t s);
 hipError_t launch_to_bf16(const float *X, int64_t n, int K, int stride, uint16_t *out,
                           hipStream_t s);
 hipError_t launch_f64_to_f32(const double *in, float *out, int64_t n, hipStream_t s);

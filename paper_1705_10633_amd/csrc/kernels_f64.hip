@@ -269,16 +269,24 @@ __global__ __launch_bounds__(256) void stats_kernel(const XT *X, int64_t n, int 
 // of sum x x^T (operand lane l = row l/16 of the group, feature l%16 of the
 // block; accumulator lane l, element v = tile row 4v + l/16, column l%16).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int STATS_THREADS = 512;
 
 template <typename XT, int NB>
-__global__ __launch_bounds__(256) void stats_mfma_kernel(const XT *X, int64_t n, int K, double *partials,
-                                                         int n_chunks)
+__global__ __launch_bounds__(STATS_THREADS) void stats_mfma_kernel(StatsSides ss, int K)
 {
+    // blocks [0, n_chunks[0]) take side 0, the rest side 1
+    const int side = (int)blockIdx.x >= ss.n_chunks[0] ? 1 : 0;
+    const XT *X = (const XT *)ss.X[side];
+    const int64_t n = ss.n[side];
+    double *partials = ss.partials[side];
+    const int n_chunks = ss.n_chunks[side];
+    const int chunk = (int)blockIdx.x - (side ? ss.n_chunks[0] : 0);
     constexpr int NT = NB * (NB + 1) / 2;
+    constexpr int NWV = STATS_THREADS / 64;       // wavefronts per block (two per SIMD)
     constexpr int PER_WAVE = (4 * NT + NB) * 64;  // doubles one wave contributes to the reduction
-    __shared__ double red[2][PER_WAVE];
+    __shared__ double red[NWV / 2][PER_WAVE];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t r0 = n * blockIdx.x / n_chunks, r1 = n * (blockIdx.x + 1) / n_chunks;
+    const int64_t r0 = n * chunk / n_chunks, r1 = n * (chunk + 1) / n_chunks;
     const int i16 = lane & 15, g = lane >> 4;
     f64x4 acc[NT];
 #pragma unroll
@@ -286,14 +294,14 @@ __global__ __launch_bounds__(256) void stats_mfma_kernel(const XT *X, int64_t n,
     double sx[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) sx[b] = 0.0;
-    // wave w takes row groups r0 + 4 (w + 4 i), GB groups at a time: all their
-    // loads are issued before any of them is multiplied
+    // wave w takes row groups r0 + 4 (w + NWV i), GB groups at a time: all
+    // their loads are issued before any of them is multiplied
     constexpr int GB = 8;
-    for (int64_t q0 = r0 + 4 * wave; q0 < r1; q0 += 16 * GB) {
+    for (int64_t q0 = r0 + 4 * wave; q0 < r1; q0 += 4 * NWV * GB) {
         double x[GB][NB];
 #pragma unroll
         for (int u = 0; u < GB; ++u) {
-            const int64_t r = q0 + 16 * u + g;
+            const int64_t r = q0 + 4 * NWV * u + g;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int f = 16 * b + i16;
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(256) void stats_mfma_kernel(const XT *X, int64_t n,
             for (int b = 0; b < NB; ++b) sx[b] += x[u][b];
         }
     }
-    // fixed-order reduction of the four waves: (0 + 2) + (1 + 3), then 0 + 1
+    // fixed-order tree reduction of the waves: w += w + NWV/2, then halves
     auto put = [&](double *dst) {
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -331,16 +339,16 @@ __global__ __launch_bounds__(256) void stats_mfma_kernel(const XT *X, int64_t n,
 #pragma unroll
         for (int b = 0; b < NB; ++b) sx[b] += src[(4 * NT + b) * 64 + lane];
     };
-    if (wave >= 2) put(red[wave - 2]);
-    __syncthreads();
-    if (wave < 2) add(red[wave]);
-    __syncthreads();
-    if (wave == 1) put(red[0]);
-    __syncthreads();
+#pragma unroll
+    for (int h = NWV / 2; h >= 1; h >>= 1) {
+        if (wave >= h && wave < 2 * h) put(red[wave - h]);
+        __syncthreads();
+        if (wave < h) add(red[wave]);
+        __syncthreads();
+    }
     if (wave != 0) return;
-    add(red[0]);
     const int E = K + K * (K + 1) / 2;
-    double *out = partials + (int64_t)blockIdx.x * E;
+    double *out = partials + (int64_t)chunk * E;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         double v = sx[b];
@@ -413,6 +421,8 @@ __global__ void advance_kernel(DevState *s, int burnin)
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         if (s->sweep >= burnin) s->pred_count += 1;
         s->fallback_rows += s->fb_count[0] + s->fb_count[1];
+        s->fb_count[0] = 0;  // the next sweep's recompute lists start empty
+        s->fb_count[1] = 0;
         s->sweep += 1;
     }
 }
@@ -443,10 +453,6 @@ __global__ void mean_from_sum_kernel(const double *accum, const int64_t *perm, i
     out[perm[t]] = c > 0 ? accum[t] / (double)c : 0.0;
 }
 
-__global__ void reset_fb_kernel(DevState *s, int side)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) s->fb_count[side] = 0;
-}
 
 __global__ void to_bf16_kernel(const float *X, int64_t n, int K, int stride, uint16_t *out)
 {
@@ -550,14 +556,14 @@ hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_
 
 int stats_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 511) / 512)); }
 
-hipError_t launch_stats(const void *X, int x_is_f64, int64_t n, int K, double *partials,
-                        int n_chunks, hipStream_t s)
+hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s)
 {
     if (K <= 64) {
         const int NB = (K + 15) / 16;
-#define BPMF_STATS_MFMA(XT, NBV)                                                                        \
-    hipLaunchKernelGGL((stats_mfma_kernel<XT, NBV>), dim3(n_chunks), dim3(256), 0, s, (const XT *)X, n, K, \
-                       partials, n_chunks)
+        const unsigned grid = (unsigned)(ss.n_chunks[0] + ss.n_chunks[1]);
+        if (grid == 0) return hipSuccess;
+#define BPMF_STATS_MFMA(XT, NBV) \
+    hipLaunchKernelGGL((stats_mfma_kernel<XT, NBV>), dim3(grid), dim3(STATS_THREADS), 0, s, ss, K)
         if (x_is_f64) {
             if (NB == 1) BPMF_STATS_MFMA(double, 1);
             else if (NB == 2) BPMF_STATS_MFMA(double, 2);
@@ -574,14 +580,67 @@ hipError_t launch_stats(const void *X, int x_is_f64, int64_t n, int K, double *p
     }
     const int nb = (K + 3) >> 2;
     const bool big = nb * (nb + 1) / 2 > 256;
-    if (x_is_f64) {
-        if (big) hipLaunchKernelGGL((stats_kernel<double, 3>), dim3(n_chunks), dim3(256), 0, s, (const double *)X, n, K, partials, n_chunks);
-        else hipLaunchKernelGGL((stats_kernel<double, 1>), dim3(n_chunks), dim3(256), 0, s, (const double *)X, n, K, partials, n_chunks);
-    } else {
-        if (big) hipLaunchKernelGGL((stats_kernel<float, 3>), dim3(n_chunks), dim3(256), 0, s, (const float *)X, n, K, partials, n_chunks);
-        else hipLaunchKernelGGL((stats_kernel<float, 1>), dim3(n_chunks), dim3(256), 0, s, (const float *)X, n, K, partials, n_chunks);
+    for (int sd = 0; sd < 2; ++sd) {
+        const int64_t n = ss.n[sd];
+        const int nc = ss.n_chunks[sd];
+        if (nc == 0) continue;
+        double *partials = ss.partials[sd];
+        if (x_is_f64) {
+            if (big) hipLaunchKernelGGL((stats_kernel<double, 3>), dim3(nc), dim3(256), 0, s, (const double *)ss.X[sd], n, K, partials, nc);
+            else hipLaunchKernelGGL((stats_kernel<double, 1>), dim3(nc), dim3(256), 0, s, (const double *)ss.X[sd], n, K, partials, nc);
+        } else {
+            if (big) hipLaunchKernelGGL((stats_kernel<float, 3>), dim3(nc), dim3(256), 0, s, (const float *)ss.X[sd], n, K, partials, nc);
+            else hipLaunchKernelGGL((stats_kernel<float, 1>), dim3(nc), dim3(256), 0, s, (const float *)ss.X[sd], n, K, partials, nc);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
+}
+
+// FP32 factors with K a multiple of 4 and at most 64: lane l of a 16-lane
+// group loads features 4l..4l+3 of each of its group's 4 pairs as one
+// 16-byte load, so a group reads its 4 U rows and 4 V rows in one round trip.
+__global__ __launch_bounds__(256) void predict_vec4_kernel(const float *U, const float *V, int K, double rbar,
+                                                           int64_t n, const int32_t *rows, const int32_t *cols,
+                                                           double *out, double *accum, const DevState *state,
+                                                           int burnin)
+{
+    constexpr int PP = 4;
+    const int64_t t0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4) * PP;
+    const int l = threadIdx.x & 15;
+    const bool lane_on = 4 * l < K;
+    const int fo = lane_on ? 4 * l : 0;  // clamped: the load stays unmasked
+    float4 a[PP], b[PP];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        const int64_t t = t0 + q < n ? t0 + q : n - 1;
+        a[q] = *(const float4 *)(U + (int64_t)rows[t] * K + fo);
+        b[q] = *(const float4 *)(V + (int64_t)cols[t] * K + fo);
+    }
+    double p[PP];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        double s = 0.0;
+        s = fma((double)a[q].x, (double)b[q].x, s);
+        s = fma((double)a[q].y, (double)b[q].y, s);
+        s = fma((double)a[q].z, (double)b[q].z, s);
+        s = fma((double)a[q].w, (double)b[q].w, s);
+        p[q] = lane_on ? s : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PP; ++q)
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) p[q] += __shfl_xor(p[q], o, 16);
+    if (l < PP && t0 + l < n) {
+        double r = p[0];
+#pragma unroll
+        for (int q = 1; q < PP; ++q) r = (l == q) ? p[q] : r;
+        r += rbar;
+        const int64_t t = t0 + l;
+        if (out) out[t] = r;
+        if (accum && state->sweep >= burnin) accum[t] += r;
+    }
 }
 
 hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, double rbar, int64_t n,
@@ -592,6 +651,9 @@ hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, dou
     if (x_is_f64)
         hipLaunchKernelGGL(predict_kernel<double>, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
                            (const double *)U, (const double *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
+    else if (K % 4 == 0 && K <= 64 && ((uintptr_t)U % 16 == 0) && ((uintptr_t)V % 16 == 0))
+        hipLaunchKernelGGL(predict_vec4_kernel, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
+                           (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
     else
         hipLaunchKernelGGL(predict_kernel<float>, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
                            (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
@@ -604,11 +666,6 @@ hipError_t launch_advance_burnin(DevState *state, int burnin, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_reset_fallback(DevState *state, int side, hipStream_t s)
-{
-    hipLaunchKernelGGL(reset_fb_kernel, dim3(1), dim3(64), 0, s, state, side);
-    return hipGetLastError();
-}
 
 hipError_t launch_to_bf16(const float *X, int64_t n, int K, int stride, uint16_t *out, hipStream_t s)
 {

@@ -32,10 +32,14 @@ constexpr int NW_THREADS = 256;
 
 // sums[e] = sum over chunks of partials[c][e]: 8 threads per entry over fixed
 // chunk ranges, combined by a fixed xor tree.
-__global__ __launch_bounds__(256) void stats_reduce_kernel(const double *partials, int n_chunks,
-                                                           int E, double *sums)
+__global__ __launch_bounds__(256) void stats_reduce_kernel(StatsSides ss, double *sums0, double *sums1,
+                                                           int E, int blocks_per_side)
 {
-    const int e = blockIdx.x * 32 + (threadIdx.x >> 3);
+    const int side = (int)blockIdx.x >= blocks_per_side ? 1 : 0;
+    const double *partials = ss.partials[side];
+    const int n_chunks = ss.n_chunks[side];
+    double *sums = side ? sums1 : sums0;
+    const int e = ((int)blockIdx.x - side * blocks_per_side) * 32 + (threadIdx.x >> 3);
     const int part = threadIdx.x & 7;
     double s = 0.0;
     if (e < E) {
@@ -227,11 +231,16 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(256) void nw_wave_kernel(const double *sums, int64_t n, int K,
+__global__ __launch_bounds__(256) void nw_wave_kernel(NwSide side0, NwSide side1, int K,
                                                       const double *mu0, double beta0, double nu0,
-                                                      const double *W0inv, DrawSrc draws, HyperDev hyp,
-                                                      DevState *state)
+                                                      const double *W0inv, DevState *state)
 {
+    // workgroup 0: users, workgroup 1: movies
+    const NwSide &sd = blockIdx.x == 0 ? side0 : side1;
+    const double *sums = sd.sums;
+    const int64_t n = sd.n;
+    const DrawSrc draws = sd.draws;
+    const HyperDev hyp = sd.hyp;
     __shared__ double Ml[NWK * NWS];             // panel broadcast, then R, then T
     __shared__ double zb[NWK * (NWK - 1) / 2];   // Bartlett normals, row-major strict lower
     __shared__ double chi2[NWK], zm[NWK], xbar[NWK], vinv[NWK], dvec[NWK], mul[NWK];
@@ -469,38 +478,31 @@ size_t nw_scratch_doubles(int K)
     return (size_t)2 * K * K + 4 * (size_t)K + (size_t)std::max(1, K * (K - 1) / 2) + 3 * (size_t)K;
 }
 
-hipError_t prepare_nw(int K)
-{
-    if (K > 0) return hipSuccess;  // the LDS variant is not used: K <= 64 runs nw_wave_kernel
-    return hipFuncSetAttribute((const void *)nw_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(nw_scratch_doubles(K) * sizeof(double)));
-}
 
-hipError_t launch_stats_reduce(const double *partials, int n_chunks, int K, double *sums, hipStream_t s)
+hipError_t launch_stats_reduce(const StatsSides &ss, double *const sums[2], int K, hipStream_t s)
 {
     const int E = K + K * (K + 1) / 2;
-    hipLaunchKernelGGL(stats_reduce_kernel, dim3((unsigned)((E + 31) / 32)), dim3(256), 0, s, partials,
-                       n_chunks, E, sums);
+    const int bps = (E + 31) / 32;
+    hipLaunchKernelGGL(stats_reduce_kernel, dim3((unsigned)(2 * bps)), dim3(256), 0, s, ss, sums[0], sums[1],
+                       E, bps);
     return hipGetLastError();
 }
 
-hipError_t launch_nw(const double *sums, int64_t n, int K, const double *mu0, double beta0, double nu0,
-                     const double *W0inv, DrawSrc draws, double *scratch, HyperDev hyp, int use_lds,
-                     DevState *state, hipStream_t s)
+hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double beta0, double nu0,
+                     const double *W0inv, DevState *state, hipStream_t s)
 {
     if (K <= NWK) {
-        hipLaunchKernelGGL(nw_wave_kernel, dim3(1), dim3(256), 0, s, sums, n, K, mu0, beta0, nu0, W0inv,
-                           draws, hyp, state);
+        hipLaunchKernelGGL(nw_wave_kernel, dim3(2), dim3(256), 0, s, sides[0], sides[1], K, mu0, beta0, nu0,
+                           W0inv, state);
         return hipGetLastError();
     }
-    size_t lds = use_lds ? nw_scratch_doubles(K) * sizeof(double) : 0;
-    if (use_lds)
-        hipLaunchKernelGGL(nw_kernel<true>, dim3(1), dim3(NW_THREADS), lds, s, sums, n, K, mu0, beta0, nu0,
-                           W0inv, draws, scratch, hyp, state);
-    else
-        hipLaunchKernelGGL(nw_kernel<false>, dim3(1), dim3(NW_THREADS), 0, s, sums, n, K, mu0, beta0, nu0,
-                           W0inv, draws, scratch, hyp, state);
-    return hipGetLastError();
+    for (int sd = 0; sd < 2; ++sd) {
+        hipLaunchKernelGGL(nw_kernel<false>, dim3(1), dim3(NW_THREADS), 0, s, sides[sd].sums, sides[sd].n, K,
+                           mu0, beta0, nu0, W0inv, sides[sd].draws, sides[sd].scratch, sides[sd].hyp, state);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace bpmf
