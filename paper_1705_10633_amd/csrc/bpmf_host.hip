@@ -65,7 +65,7 @@ struct WsLayout {
 };
 
 struct Offsets {
-    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], mu0, w0inv,
+    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], nwd[2], mu0, w0inv,
         order[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
@@ -94,6 +94,7 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
         o.lamf[s] = w.add(sizeof(float) * K * K);
         o.lmuf[s] = w.add(sizeof(float) * K);
         o.lamt[s] = w.add(sizeof(float) * (size_t)padded_k(K) * (padded_k(K) + 3) / 2);
+        o.nwd[s] = w.add(sizeof(double) * (size_t)(2 * K + K * (K - 1) / 2));
         o.order[s] = w.add(sizeof(int32_t) * n[s]);
         o.fblist[s] = w.add(mk ? sizeof(int32_t) * n[s] : 0);
         // BF16 copy plus one all-zero row (the gather target past a row's end)
@@ -350,6 +351,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
     } while (0)
 
     HIP_OK_C(prepare_rows_f64(K));
+    HIP_OK_C(prepare_nw());
     HIP_OK_C(launch_fill_zero(c->ws, off.total - kAlign, s));
 
     // mean rating
@@ -482,9 +484,16 @@ static bpmf_status enqueue_hyper(bpmf_ctx *c, const DrawSrc &d0, const DrawSrc &
     ss.X[1] = c->dV;
     ss.n[0] = c->R.M;
     ss.n[1] = c->R.N;
+    // with device draws and K <= 64 the statistics launch also draws the
+    // Normal-Wishart randoms, and the hyper step reads them like a tape
+    const bool pre = !d0.tape_nw && K <= 64;
+    ss.with_draws = pre ? 1 : 0;
+    ss.nu0 = c->nu0;
     for (int sd = 0; sd < 2; ++sd) {
         ss.partials[sd] = c->at<double>(c->off.partials[sd]);
         ss.n_chunks[sd] = c->n_chunks[sd];
+        ss.draw_out[sd] = c->at<double>(c->off.nwd[sd]);
+        ss.draws[sd] = sd == 0 ? d0 : d1;
     }
     double *const sums[2] = {c->at<double>(c->off.sums[0]), c->at<double>(c->off.sums[1])};
     hipEvent_t t0 = time_begin(c, s);
@@ -497,6 +506,7 @@ static bpmf_status enqueue_hyper(bpmf_ctx *c, const DrawSrc &d0, const DrawSrc &
         nw[sd].sums = sums[sd];
         nw[sd].n = ss.n[sd];
         nw[sd].draws = *d[sd];
+        if (pre) nw[sd].draws.tape_nw = ss.draw_out[sd];
         nw[sd].scratch = c->at<double>(c->off.scratch[sd]);
         nw[sd].hyp = c->hyp[sd];
     }

@@ -97,6 +97,13 @@ struct StatsSides {
     int64_t n[2];          // rows
     double *partials[2];   // per-chunk partial sums
     int n_chunks[2];
+    // Optional (K <= 64, device draws): two more blocks draw each side's
+    // Normal-Wishart randoms into draw_out[side] in the tape layout
+    // [K chi^2][K(K-1)/2 Bartlett normals][K mean normals].
+    double *draw_out[2];
+    DrawSrc draws[2];
+    double nu0;
+    int with_draws;
 };
 struct NwSide {
     const double *sums;    // sum x (K) then sum x x^T (packed lower, K(K+1)/2)
@@ -123,6 +130,7 @@ hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, dou
                           double *accum, const DevState *state, int burnin, hipStream_t s);
 hipError_t launch_advance_burnin(DevState *state, int burnin, hipStream_t s);
 hipError_t launch_lambda_tri(HyperDev hyp, int K, int KP, hipStream_t s);
+hipError_t prepare_nw();
 hipError_t launch_to_bf16(const float *X, int64_t n, int K, int stride, uint16_t *out,
                           hipStream_t s);
 hipError_t launch_f64_to_f32(const double *in, float *out, int64_t n, hipStream_t s);

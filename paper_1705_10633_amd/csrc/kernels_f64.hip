@@ -271,9 +271,39 @@ __global__ __launch_bounds__(256) void stats_kernel(const XT *X, int64_t n, int 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int STATS_THREADS = 512;
 
+// The Normal-Wishart randoms of one half-sweep, in the tape layout (see the
+// hyper-parameter kernel): K chi^2(nu* - k) by Marsaglia-Tsang, then the
+// Bartlett and mean normals (normal q of a stream is member q % 2 of the
+// Box-Muller pair q / 2).
+__device__ void nw_draws_block(const DrawSrc &d, int K, double nstar, double *out)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int NB = K * (K - 1) / 2;
+    const uint32_t h = half_sweep_index(d);
+    for (int k = tid; k < K; k += nt) out[k] = 2.0 * gamma_mt(d.seed, h, (uint32_t)k, 0.5 * (nstar - (double)k));
+    for (int p = tid; 2 * p < NB; p += nt) {
+        double z0, z1;
+        box_muller_f64(philox4x32_10(ctr4((uint32_t)p, 0u, h, 1u), d.seed), z0, z1);
+        out[K + 2 * p] = z0;
+        if (2 * p + 1 < NB) out[K + 2 * p + 1] = z1;
+    }
+    for (int p = tid; 2 * p < K; p += nt) {
+        double z0, z1;
+        box_muller_f64(philox4x32_10(ctr4((uint32_t)p, 0u, h, 2u), d.seed), z0, z1);
+        out[K + NB + 2 * p] = z0;
+        if (2 * p + 1 < K) out[K + NB + 2 * p + 1] = z1;
+    }
+}
+
 template <typename XT, int NB>
 __global__ __launch_bounds__(STATS_THREADS) void stats_mfma_kernel(StatsSides ss, int K)
 {
+    const int nstat = ss.n_chunks[0] + ss.n_chunks[1];
+    if ((int)blockIdx.x >= nstat) {
+        const int sd = (int)blockIdx.x - nstat;
+        nw_draws_block(ss.draws[sd], K, ss.nu0 + (double)ss.n[sd], ss.draw_out[sd]);
+        return;
+    }
     // blocks [0, n_chunks[0]) take side 0, the rest side 1
     const int side = (int)blockIdx.x >= ss.n_chunks[0] ? 1 : 0;
     const XT *X = (const XT *)ss.X[side];
@@ -560,7 +590,7 @@ hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s
 {
     if (K <= 64) {
         const int NB = (K + 15) / 16;
-        const unsigned grid = (unsigned)(ss.n_chunks[0] + ss.n_chunks[1]);
+        const unsigned grid = (unsigned)(ss.n_chunks[0] + ss.n_chunks[1] + (ss.with_draws ? 2 : 0));
         if (grid == 0) return hipSuccess;
 #define BPMF_STATS_MFMA(XT, NBV) \
     hipLaunchKernelGGL((stats_mfma_kernel<XT, NBV>), dim3(grid), dim3(STATS_THREADS), 0, s, ss, K)

@@ -393,6 +393,7 @@ __global__ __launch_bounds__(256) void nw_wave_kernel(NwSide side0, NwSide side1
     }
     __syncthreads();
     if (w0) {
+        __asm__ volatile("" ::: "memory");  // dvec written by lane 0
         double mu = 0.0;
         if (lane < K) {
             mu = (beta0 * mu0[lane] + dn * xbar[lane]) / bstar + dvec[lane];
@@ -454,6 +455,244 @@ __global__ __launch_bounds__(256) void nw_wave_kernel(NwSide side0, NwSide side1
     if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
 }
 
+// ---------------------------------------------------------------------------
+// K <= 64, compact form: P, R and T live in LDS (padded to 64, identity in
+// the padding).  One wavefront runs the three sequential parts with one matrix
+// row (or column) per lane and an 8-wide panel in registers: the
+// factorisation from the last pivot, the solve R^T T = A and the mean solve;
+// all four wavefronts draw the random numbers, form P and compute
+// Lambda = T T^T.  The loops over panels and rows are not unrolled, so the
+// code stays small enough for the instruction cache.
+// ---------------------------------------------------------------------------
+constexpr int NCS = NWK + 1;  // LDS row stride (doubles) of P/R and T
+
+constexpr int NSUMS = NWK + NWK * (NWK + 1) / 2;  // sum x and packed sum x x^T at K = 64
+
+size_t nw_compact_lds_bytes()
+{
+    return sizeof(double) * ((size_t)2 * NWK * NCS + 10 * NWK + NSUMS);
+}
+
+__global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide side1, int K,
+                                                         const double *mu0, double beta0, double nu0,
+                                                         const double *W0inv, DevState *state)
+{
+    extern __shared__ double lds[];
+    double *Pm = lds;                  // P, then R in its upper triangle (row-major)
+    double *Tm = Pm + NWK * NCS;       // A, then T (lower, row-major)
+    double *xbar = Tm + NWK * NCS;
+    double *chi2 = xbar + NWK, *zm = chi2 + NWK, *vinv = zm + NWK, *dvec = vinv + NWK, *mul = dvec + NWK;
+    double *lpart = mul + NWK;         // 4 x 64 partial sums of Lambda mu
+    double *sl = lpart + 4 * NWK;      // the side's sums, copied once
+    __shared__ int s_flag;
+    const NwSide &sd = blockIdx.x == 0 ? side0 : side1;
+    const double *sums = sd.sums;
+    const int64_t n = sd.n;
+    const DrawSrc draws = sd.draws;
+    const HyperDev hyp = sd.hyp;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int NB = K * (K - 1) / 2;
+    const double dn = (double)n, bstar = beta0 + dn, nstar = nu0 + dn;
+
+    if (tid == 0) s_flag = 0;
+    for (int e = tid; e < NWK * NCS; e += 256) Tm[e] = 0.0;
+    for (int e = tid; e < K + K * (K + 1) / 2; e += 256) sl[e] = sums[e];
+    __syncthreads();
+    for (int a = tid; a < NWK; a += 256) xbar[a] = (a < K && n > 0) ? sl[a] / dn : 0.0;
+    // draws: chi^2 of the Bartlett diagonal, the strict lower part of A (row-
+    // major order q = r (r - 1) / 2 + c) straight into Tm, the mean normals
+    if (draws.tape_nw) {
+        for (int k = tid; k < K; k += 256) chi2[k] = draws.tape_nw[k];
+        for (int q = tid; q < NB; q += 256) {
+            int r = (int)((1.0 + sqrt(1.0 + 8.0 * q)) * 0.5);
+            while (r * (r - 1) / 2 > q) --r;
+            while ((r + 1) * r / 2 <= q) ++r;
+            Tm[r * NCS + (q - r * (r - 1) / 2)] = draws.tape_nw[K + q];
+        }
+        for (int q = tid; q < K; q += 256) zm[q] = draws.tape_nw[K + NB + q];
+    } else {
+        const uint32_t h = half_sweep_index(draws);
+        for (int k = tid; k < K; k += 256)
+            chi2[k] = 2.0 * gamma_mt(draws.seed, h, (uint32_t)k, 0.5 * (nstar - (double)k));
+        // normal q of a stream is member q % 2 of Box-Muller pair q / 2
+        for (int p = tid; 2 * p < NB; p += 256) {
+            double z[2];
+            box_muller_f64(philox4x32_10(ctr4((uint32_t)p, 0u, h, 1u), draws.seed), z[0], z[1]);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int q = 2 * p + u;
+                if (q < NB) {
+                    int r = (int)((1.0 + sqrt(1.0 + 8.0 * q)) * 0.5);
+                    while (r * (r - 1) / 2 > q) --r;
+                    while ((r + 1) * r / 2 <= q) ++r;
+                    Tm[r * NCS + (q - r * (r - 1) / 2)] = z[u];
+                }
+            }
+        }
+        for (int p = tid; 2 * p < K; p += 256) {
+            double z0, z1;
+            box_muller_f64(philox4x32_10(ctr4((uint32_t)p, 0u, h, 2u), draws.seed), z0, z1);
+            zm[2 * p] = z0;
+            if (2 * p + 1 < K) zm[2 * p + 1] = z1;
+        }
+    }
+    // P = W0^{-1} + S + coef (xbar - mu0)(xbar - mu0)^T, identity padding
+    {
+        const double coef = beta0 * dn / bstar;
+        // unrolled by 4 so the loads of four entries are in flight together
+#pragma unroll 4
+        for (int e = tid; e < NWK * NWK; e += 256) {
+            const int i = e >> 6, j = e & 63;
+            double v = (i == j) ? 1.0 : 0.0;
+            if (i < K && j < K) {
+                const int hi = i > j ? i : j, lo = i > j ? j : i;
+                const double S = sl[K + hi * (hi + 1) / 2 + lo] - dn * xbar[i] * xbar[j];
+                v = W0inv[i * K + j] + S + coef * (xbar[i] - mu0[i]) * (xbar[j] - mu0[j]);
+            }
+            Pm[i * NCS + j] = v;
+        }
+    }
+    __syncthreads();
+    for (int m = tid; m < NWK; m += 256) Tm[m * NCS + m] = m < K ? sqrt(chi2[m]) : 1.0;
+
+    // P = R R^T from the last pivot up, 8-column panels.  Wavefront 0 factors
+    // a panel with lane i holding row i; then all four wavefronts update the
+    // leading block (columns j < c0 split over the wavefronts).
+    for (int c0 = NWK - NPW; c0 >= 0; c0 -= NPW) {
+        if (wave == 0) {
+            double a[NPW];
+#pragma unroll
+            for (int m = 0; m < NPW; ++m) a[m] = Pm[lane * NCS + c0 + m];
+#pragma unroll
+            for (int kk = NPW - 1; kk >= 0; --kk) {
+                const int k = c0 + kk;
+                double pkk = readlane_d(a[kk], k);
+                if (!(pkk > 0.0) || !(pkk < INFINITY)) {
+                    if (lane == 0) s_flag = 1;
+                    pkk = 1.0;
+                }
+                // 1/sqrt(pkk): hardware estimate refined by three Newton steps
+                double y = __builtin_amdgcn_rsq(pkk);
+                y = y * fma(-0.5 * pkk * y, y, 1.5);
+                y = y * fma(-0.5 * pkk * y, y, 1.5);
+                y = y * fma(-0.5 * pkk * y, y, 1.5);
+                a[kk] *= y;  // lanes i < k: R_ik; lane k: R_kk
+                if (lane == 0) vinv[k] = y;
+#pragma unroll
+                for (int jj = 0; jj < kk; ++jj) a[jj] = fma(-a[kk], readlane_d(a[kk], c0 + jj), a[jj]);
+            }
+#pragma unroll
+            for (int m = 0; m < NPW; ++m) Pm[lane * NCS + c0 + m] = a[m];
+        }
+        if (c0 == 0) break;
+        __syncthreads();
+        {
+            double a[NPW];
+#pragma unroll
+            for (int m = 0; m < NPW; ++m) a[m] = Pm[lane * NCS + c0 + m];
+            // leading block: P_ij -= sum over the panel of R_im R_jm, j < c0
+#pragma unroll 2
+            for (int j = wave; j < c0; j += 4) {
+                const double *rj = Pm + j * NCS + c0;
+                double t = Pm[lane * NCS + j];
+#pragma unroll
+                for (int m = 0; m < NPW; ++m) t = fma(-a[m], rj[m], t);
+                Pm[lane * NCS + j] = t;
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // R^T T = A, forward over 8-row blocks with lane m holding column m:
+    // wavefront 0 solves a block's diagonal part, then all four wavefronts
+    // update the rows below (split over the wavefronts)
+    for (int i0 = 0; i0 < NWK; i0 += NPW) {
+        if (wave == 0) {
+            double t[NPW];
+#pragma unroll
+            for (int q = 0; q < NPW; ++q) t[q] = Tm[(i0 + q) * NCS + lane];
+#pragma unroll
+            for (int q = 0; q < NPW; ++q) {
+                t[q] *= vinv[i0 + q];
+#pragma unroll
+                for (int q2 = q + 1; q2 < NPW; ++q2) t[q2] = fma(-Pm[(i0 + q) * NCS + i0 + q2], t[q], t[q2]);
+            }
+#pragma unroll
+            for (int q = 0; q < NPW; ++q) Tm[(i0 + q) * NCS + lane] = t[q];
+        }
+        if (i0 + NPW == NWK) break;
+        __syncthreads();
+        {
+            double t[NPW];
+#pragma unroll
+            for (int q = 0; q < NPW; ++q) t[q] = Tm[(i0 + q) * NCS + lane];
+#pragma unroll 2
+            for (int i = i0 + NPW + wave; i < NWK; i += 4) {
+                double u = Tm[i * NCS + lane];
+#pragma unroll
+                for (int q = 0; q < NPW; ++q) u = fma(-Pm[(i0 + q) * NCS + i], t[q], u);
+                Tm[i * NCS + lane] = u;
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // mean: T^T d = z / sqrt(beta*), backward; lane i holds right-hand side i
+        const double it = 1.0 / Tm[lane * NCS + lane];
+        double rhs = lane < K ? zm[lane] * (1.0 / sqrt(bstar)) : 0.0;
+        for (int k = NWK - 1; k >= 0; --k) {
+            const double dk = readlane_d(rhs * it, k);
+            if (lane == 0) dvec[k] = dk;
+            rhs = fma(-Tm[k * NCS + lane], dk, rhs);
+        }
+        __asm__ volatile("" ::: "memory");  // dvec written by lane 0
+        double mu = 0.0;
+        if (lane < K) {
+            mu = (beta0 * mu0[lane] + dn * xbar[lane]) / bstar + dvec[lane];
+            hyp.mu[lane] = mu;
+        }
+        mul[lane] = mu;
+    }
+    __syncthreads();
+
+    // Lambda = T T^T: thread (a, 16-column block of its wave); T[c][m] = 0 for m > c
+    {
+        const int a = lane, cb = 16 * wave;
+        double acc[16];
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) acc[cc] = 0.0;
+#pragma unroll 2
+        for (int m = 0; m < cb + 16; ++m) {
+            const double ta = Tm[a * NCS + m];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) acc[cc] = fma(ta, Tm[(cb + cc) * NCS + m], acc[cc]);
+        }
+        const int KPm = K <= 32 ? 32 : 64;  // padded size of the mixed row kernel
+        double lmu = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+            const int c = cb + cc;
+            if (a < K && c < K) {
+                hyp.Lambda[a * K + c] = acc[cc];
+                hyp.Lambda_f[a * K + c] = (float)acc[cc];
+            }
+            if (c <= a && a < KPm)
+                hyp.Lambda_tri[a * (a + 1) / 2 + c] = (a < K && c < K) ? (float)acc[cc] : (a == c ? 1.0f : 0.0f);
+            lmu = fma(acc[cc], mul[c], lmu);
+        }
+        lpart[wave * NWK + a] = lmu;
+    }
+    __syncthreads();
+    if (wave == 0 && lane < K) {
+        // the four 16-column partial sums of row lane, in column order
+        const double lmu = ((lpart[lane] + lpart[NWK + lane]) + lpart[2 * NWK + lane]) + lpart[3 * NWK + lane];
+        hyp.Lmu[lane] = lmu;
+        hyp.Lmu_f[lane] = (float)lmu;
+    }
+    if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
+}
+
 // Lambda_tri from Lambda_f (after a state restore).
 __global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, int KP)
 {
@@ -465,6 +704,12 @@ __global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, in
 }
 
 }  // namespace
+
+hipError_t prepare_nw()
+{
+    return hipFuncSetAttribute((const void *)nw_compact_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)nw_compact_lds_bytes());
+}
 
 hipError_t launch_lambda_tri(HyperDev hyp, int K, int KP, hipStream_t s)
 {
@@ -492,8 +737,8 @@ hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double bet
                      const double *W0inv, DevState *state, hipStream_t s)
 {
     if (K <= NWK) {
-        hipLaunchKernelGGL(nw_wave_kernel, dim3(2), dim3(256), 0, s, sides[0], sides[1], K, mu0, beta0, nu0,
-                           W0inv, state);
+        hipLaunchKernelGGL(nw_compact_kernel, dim3(2), dim3(256), nw_compact_lds_bytes(), s, sides[0], sides[1],
+                           K, mu0, beta0, nu0, W0inv, state);
         return hipGetLastError();
     }
     for (int sd = 0; sd < 2; ++sd) {
