@@ -210,249 +210,14 @@ __global__ __launch_bounds__(NW_THREADS) void nw_kernel(const double *sums, int6
     if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
 }
 
-// ---------------------------------------------------------------------------
-// K <= 64: the same computation by one wavefront that keeps one matrix row
-// (or column) per lane in FP64 registers.  The factorisation, the solve for T
-// and the product T T^T are unrolled over the padded size 64, so every step
-// is a short run of register FMAs with operands broadcast by readlane or
-// read from LDS, and there is no barrier inside a step.  The other three
-// wavefronts of the workgroup only help draw the random numbers; they pass
-// the barriers with the first one.  Padding rows and columns (K..63) carry
-// the identity and do not touch the leading K x K block.
-// ---------------------------------------------------------------------------
-constexpr int NWK = 64;       // padded size
-constexpr int NWS = NWK + 1;  // LDS row stride (doubles): conflict-free row-per-lane access
-constexpr int NPW = 8;        // factorisation panel width
+constexpr int NWK = 64;       // padded size (K <= 64)
+constexpr int NPW = 8;        // panel width
 
 __device__ __forceinline__ double readlane_d(double v, int l)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
-}
-
-__global__ __launch_bounds__(256) void nw_wave_kernel(NwSide side0, NwSide side1, int K,
-                                                      const double *mu0, double beta0, double nu0,
-                                                      const double *W0inv, DevState *state)
-{
-    // workgroup 0: users, workgroup 1: movies
-    const NwSide &sd = blockIdx.x == 0 ? side0 : side1;
-    const double *sums = sd.sums;
-    const int64_t n = sd.n;
-    const DrawSrc draws = sd.draws;
-    const HyperDev hyp = sd.hyp;
-    __shared__ double Ml[NWK * NWS];             // panel broadcast, then R, then T
-    __shared__ double zb[NWK * (NWK - 1) / 2];   // Bartlett normals, row-major strict lower
-    __shared__ double chi2[NWK], zm[NWK], xbar[NWK], vinv[NWK], dvec[NWK], mul[NWK];
-    __shared__ int s_flag;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const bool w0 = tid < 64;
-    const int NB = K * (K - 1) / 2;
-    const double dn = (double)n, bstar = beta0 + dn, nstar = nu0 + dn;
-
-    if (tid == 0) s_flag = 0;
-    if (draws.tape_nw) {
-        for (int k = tid; k < K; k += 256) chi2[k] = draws.tape_nw[k];
-        for (int q = tid; q < NB; q += 256) zb[q] = draws.tape_nw[K + q];
-        for (int q = tid; q < K; q += 256) zm[q] = draws.tape_nw[K + NB + q];
-    } else {
-        const uint32_t h = half_sweep_index(draws);
-        for (int k = tid; k < K; k += 256)
-            chi2[k] = 2.0 * gamma_mt(draws.seed, h, (uint32_t)k, 0.5 * (nstar - (double)k));
-        // normal q of a stream is member q % 2 of Box-Muller pair q / 2
-        for (int p = tid; 2 * p < NB; p += 256) {
-            double z0, z1;
-            box_muller_f64(philox4x32_10(ctr4((uint32_t)p, 0u, h, 1u), draws.seed), z0, z1);
-            zb[2 * p] = z0;
-            if (2 * p + 1 < NB) zb[2 * p + 1] = z1;
-        }
-        for (int p = tid; 2 * p < K; p += 256) {
-            double z0, z1;
-            box_muller_f64(philox4x32_10(ctr4((uint32_t)p, 0u, h, 2u), draws.seed), z0, z1);
-            zm[2 * p] = z0;
-            if (2 * p + 1 < K) zm[2 * p + 1] = z1;
-        }
-    }
-    for (int a = tid; a < NWK; a += 256) xbar[a] = (a < K && n > 0) ? sums[a] / dn : 0.0;
-    __syncthreads();
-
-    // row `lane` of P = W0^{-1} + S + coef (xbar - mu0)(xbar - mu0)^T
-    double A[NWK];
-    if (w0) {
-        const double coef = beta0 * dn / bstar;
-        const int i = lane;
-        const double xi = xbar[i];
-        const double di = i < K ? xi - mu0[i] : 0.0;
-        // row i of the packed lower triangle of sum x x^T, and its column i
-        // (entries (j, i), j > i, at j (j + 1) / 2 + i): constant offsets
-        const int ic = i < K ? i : 0;
-        const double *srow = sums + K + ic * (ic + 1) / 2;
-        const double *scol = sums + K + ic;
-        const double *wrow = W0inv + (size_t)ic * K;
-#pragma unroll
-        for (int j = 0; j < NWK; ++j) {
-            double v = (i == j) ? 1.0 : 0.0;
-            if (i < K && j < K) {
-                const double sxx = j <= i ? srow[j] : scol[j * (j + 1) / 2];
-                const double S = sxx - dn * xi * xbar[j];
-                v = wrow[j] + S + coef * di * (xbar[j] - mu0[j]);
-            }
-            A[j] = v;
-            // compiler-only memory fence: keeps all 64 entries' loads from
-            // being hoisted into registers at once
-            if ((j & 7) == 7) __asm__ volatile("" ::: "memory");
-        }
-    }
-
-    // P = R R^T, R upper triangular, from the last pivot up, in panels of 8
-    // columns.  Lane i ends with R_ik in A[k] for k >= i.
-    double *pbuf = Ml;
-#pragma unroll
-    for (int c0 = NWK - NPW; c0 >= 0; c0 -= NPW) {
-        if (w0) {
-#pragma unroll
-            for (int k = c0 + NPW - 1; k >= c0; --k) {
-                double pkk = readlane_d(A[k], k);
-                if (!(pkk > 0.0) || !(pkk < INFINITY)) {
-                    if (lane == 0) s_flag = 1;
-                    pkk = 1.0;
-                }
-                const double r = sqrt(pkk);
-                const double inv = 1.0 / r;
-                A[k] *= inv;  // lanes i < k: R_ik; lane k: R_kk
-                if (lane == 0) vinv[k] = inv;
-#pragma unroll
-                for (int j = c0; j < k; ++j) A[j] = fma(-A[k], readlane_d(A[k], j), A[j]);
-            }
-            if (c0 > 0) {
-#pragma unroll
-                for (int m = 0; m < NPW; ++m) pbuf[lane * NPW + m] = A[c0 + m];
-            }
-        }
-        if (c0 > 0) {
-            __syncthreads();
-            if (w0) {
-                // leading block: A_ij -= sum over the panel of R_im R_jm
-#pragma unroll
-                for (int j = 0; j < c0; ++j) {
-                    double t = A[j];
-#pragma unroll
-                    for (int m = 0; m < NPW; ++m) t = fma(-A[c0 + m], pbuf[j * NPW + m], t);
-                    A[j] = t;
-                    if ((j & 3) == 3) __asm__ volatile("" ::: "memory");
-                }
-            }
-            __syncthreads();
-        }
-    }
-    // R to LDS, row-major
-    if (w0) {
-#pragma unroll
-        for (int j = 0; j < NWK; ++j) Ml[lane * NWS + j] = A[j];
-    }
-    __syncthreads();
-
-    // column `lane` of T from R^T T = A (Bartlett factor A), forward in rows
-    double T[NWK];
-    if (w0) {
-        const int m = lane;
-#pragma unroll
-        for (int r = 0; r < NWK; ++r) {
-            double v = (r == m) ? 1.0 : 0.0;
-            if (m < K && r < K && r >= m) {
-                const int q = r > m ? r * (r - 1) / 2 + m : 0;
-                v = (r == m) ? sqrt(chi2[m]) : zb[q];
-            }
-            T[r] = v;
-        }
-#pragma unroll
-        for (int j = 0; j < NWK; ++j) {
-            T[j] *= vinv[j];
-#pragma unroll
-            for (int r = j + 1; r < NWK; ++r) T[r] = fma(-Ml[j * NWS + r], T[j], T[r]);
-            __asm__ volatile("" ::: "memory");
-        }
-    }
-    __syncthreads();
-    if (w0) {
-#pragma unroll
-        for (int r = 0; r < NWK; ++r) Ml[r * NWS + lane] = T[r];
-    }
-    __syncthreads();
-
-    // mean: T^T d = z / sqrt(beta*), backward; lane i holds the right-hand side i
-    if (w0) {
-        const double it = 1.0 / Ml[lane * NWS + lane];
-        double rhs = lane < K ? zm[lane] * (1.0 / sqrt(bstar)) : 0.0;
-#pragma unroll
-        for (int k = NWK - 1; k >= 0; --k) {
-            const double dk = readlane_d(rhs * it, k);
-            if (lane == 0) dvec[k] = dk;
-            rhs = fma(-Ml[k * NWS + lane], dk, rhs);
-        }
-    }
-    __syncthreads();
-    if (w0) {
-        __asm__ volatile("" ::: "memory");  // dvec written by lane 0
-        double mu = 0.0;
-        if (lane < K) {
-            mu = (beta0 * mu0[lane] + dn * xbar[lane]) / bstar + dvec[lane];
-            hyp.mu[lane] = mu;
-        }
-        mul[lane] = mu;
-    }
-    __syncthreads();
-
-    // row `lane` of Lambda = T T^T (T[c][m] = 0 for m > c), and Lambda mu
-    if (w0) {
-        const int a = lane;
-        double *lrow = hyp.Lambda + (size_t)(a < K ? a : 0) * K;
-        float *lfrow = hyp.Lambda_f + (size_t)(a < K ? a : 0) * K;
-        const int KPm = K <= 32 ? 32 : 64;  // padded size of the mixed row kernel
-        float *trow = hyp.Lambda_tri + (a < KPm ? a * (a + 1) / 2 : 0);
-        double lmu = 0.0;
-#pragma unroll
-        for (int cb = 0; cb < NWK; cb += 16) {
-            double acc[16];
-#pragma unroll
-            for (int cc = 0; cc < 16; ++cc) acc[cc] = 0.0;
-            // m < cb: T[c][m] is in the lower triangle for every c of the block.
-            // Kept as a loop (unrolled by 2) so the LDS loads are not all
-            // hoisted into registers at once.
-#pragma unroll 2
-            for (int m = 0; m < cb; ++m) {
-                const double t = Ml[a * NWS + m];
-#pragma unroll
-                for (int cc = 0; cc < 16; ++cc) acc[cc] = fma(t, Ml[(cb + cc) * NWS + m], acc[cc]);
-            }
-            // m in [cb, cb + 16): T[c][m] = 0 for m > c
-#pragma unroll
-            for (int mm = 0; mm < 16; ++mm) {
-                const double t = Ml[a * NWS + cb + mm];
-#pragma unroll
-                for (int cc = mm; cc < 16; ++cc) acc[cc] = fma(t, Ml[(cb + cc) * NWS + cb + mm], acc[cc]);
-                if ((mm & 3) == 3) __asm__ volatile("" ::: "memory");
-            }
-#pragma unroll
-            for (int cc = 0; cc < 16; ++cc) {
-                const int c = cb + cc;
-                if (a < K && c < K) {
-                    lrow[c] = acc[cc];
-                    lfrow[c] = (float)acc[cc];
-                }
-                if (c <= a && a < KPm)
-                    trow[c] = (a < K && c < K) ? (float)acc[cc] : (a == c ? 1.0f : 0.0f);
-                lmu = fma(acc[cc], mul[c], lmu);
-            }
-            // pin the running sum here, so the block's 16 entries die now
-            __asm__ volatile("" : "+v"(lmu));
-        }
-        if (a < K) {
-            hyp.Lmu[a] = lmu;
-            hyp.Lmu_f[a] = (float)lmu;
-        }
-    }
-    if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
 }
 
 // ---------------------------------------------------------------------------
