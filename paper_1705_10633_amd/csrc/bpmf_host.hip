@@ -70,9 +70,15 @@ struct Offsets {
     size_t total;
 };
 
-static int padded_k(int K) { return K <= 32 ? 32 : 64; }
+static int padded_k(int K) { return K <= 32 ? 32 : (K <= 64 ? 64 : 128); }
 
-static bool mixed_supported(int K) { return K <= 64; }
+// Mixed-precision row kernels: one wavefront per row for K <= 64 (FP32 or
+// BF16 gathers); a four-wavefront workgroup per row for 64 < K <= 128 (BF16
+// gathers only).  Other cases use FP64 row arithmetic on FP32 storage.
+static bool mixed_supported(int K, int precision)
+{
+    return K <= 64 || (precision == BPMF_BF16 && K <= 128);
+}
 
 static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_test)
 {
@@ -81,7 +87,7 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
     const int K = p->K;
     const int64_t n[2] = {R->M, R->N};
     const bool mixed = p->precision != BPMF_FP64;
-    const bool mk = mixed && mixed_supported(K);
+    const bool mk = mixed && mixed_supported(K, p->precision);
     o.state = w.add(sizeof(DevState));
     for (int s = 0; s < 2; ++s) {
         const int nc = stats_chunks(n[s]);
@@ -418,7 +424,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         HIP_OK_C(launch_f64_to_f32((const double *)R->d_col_val, c->at<float>(off.valsf[1]), R->nnz, s));
     }
     // BF16 copies of the initial factors
-    if (p->precision == BPMF_BF16 && mixed_supported(K)) {
+    if (p->precision == BPMF_BF16 && mixed_supported(K, p->precision)) {
         HIP_OK_C(launch_to_bf16((const float *)d_U, R->M, K, c->KP, c->at<uint16_t>(off.shadow[0]), s));
         HIP_OK_C(launch_to_bf16((const float *)d_V, R->N, K, c->KP, c->at<uint16_t>(off.shadow[1]), s));
     }
@@ -512,6 +518,8 @@ static bpmf_status enqueue_hyper(bpmf_ctx *c, const DrawSrc &d0, const DrawSrc &
     }
     t0 = time_begin(c, s);
     HIP_OK(launch_nw(nw, K, c->at<double>(c->off.mu0), c->beta0, c->nu0, c->at<double>(c->off.w0inv), c->state, s));
+    if (K > 64 && !c->x_f64() && mixed_supported(K, c->precision))
+        for (int sd = 0; sd < 2; ++sd) HIP_OK(launch_lambda_tri(c->hyp[sd], K, c->KP, s));  // the K = 128 kernel's Lambda
     time_end(c, 1, t0, s);
     return BPMF_OK;
 }
@@ -523,7 +531,7 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
     const bpmf_ratings &R = c->R;
     const int64_t n = side == 0 ? R.M : R.N;
     const bool f64 = c->precision == BPMF_FP64;
-    const bool mixed_kernel = !f64 && mixed_supported(K);
+    const bool mixed_kernel = !f64 && mixed_supported(K, c->precision);
     SideArgs a;
     a.n_rows = n;
     a.n_other = side == 0 ? R.N : R.M;
@@ -558,8 +566,12 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
         return BPMF_OK;
     }
     t0 = time_begin(c, s);
-    HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d,
-                             c->at<int32_t>(c->off.fblist[side]), c->state, s));
+    if (K <= 64)
+        HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d,
+                                 c->at<int32_t>(c->off.fblist[side]), c->state, s));
+    else
+        HIP_OK(launch_rows_mixed128(a, K, c->alpha, c->rbar, c->hyp[side], d, c->at<int32_t>(c->off.fblist[side]),
+                                    c->state, s));
     time_end(c, 2 + side, t0, s);
     t0 = time_begin(c, s);
     HIP_OK(launch_rows_f64(a, K, c->alpha, c->rbar, c->hyp[side], d, c->at<int32_t>(c->off.fblist[side]),
@@ -747,7 +759,7 @@ static bpmf_status state_copy(bpmf_ctx *c, char *h, bool save, hipStream_t s)
             HIP_OK(launch_f64_to_f32(c->hyp[sd].Lmu, c->hyp[sd].Lmu_f, K, s));
             HIP_OK(launch_lambda_tri(c->hyp[sd], K, c->KP, s));
         }
-        if (c->precision == BPMF_BF16 && mixed_supported(K)) {
+        if (c->precision == BPMF_BF16 && mixed_supported(K, c->precision)) {
             HIP_OK(launch_to_bf16((const float *)c->dU, c->R.M, K, c->KP, c->at<uint16_t>(c->off.shadow[0]), s));
             HIP_OK(launch_to_bf16((const float *)c->dV, c->R.N, K, c->KP, c->at<uint16_t>(c->off.shadow[1]), s));
         }

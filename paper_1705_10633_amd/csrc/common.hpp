@@ -122,6 +122,8 @@ hipError_t launch_rows_f64(const SideArgs &a, int K, double alpha, double rbar,
                            HyperDev hyp, DrawSrc draws, const int32_t *list,
                            const int32_t *list_count, int64_t max_rows, int x_is_f32,
                            DevState *state, hipStream_t s);
+hipError_t launch_rows_mixed128(const SideArgs &a, int K, double alpha, double rbar, HyperDev hyp,
+                                DrawSrc draws, int32_t *fb_list, DevState *state, hipStream_t s);
 hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double alpha,
                              double rbar, HyperDev hyp, DrawSrc draws, int32_t *fb_list,
                              DevState *state, hipStream_t s);

@@ -1,0 +1,356 @@
+// kernels_mixed128.hip -- mixed-precision row update for 64 < K <= 128 (BF16
+// gathers), one 256-thread workgroup per row.
+//
+// The same conditional as the other row kernels (paper: Section 2 and
+// Algorithm 1; Cholesky instead of an inverse, Section 3.1):
+//   P = Lambda + alpha G,  G = sum_{j in Omega_i} v_j v_j^T,
+//   b = Lambda mu + alpha sum_j (r_ij - rbar) v_j,  x_i = L^{-T}(L^{-1} b + z_i),
+// with K padded to 128 (identity block) and P factored in 64-blocks:
+//   L11 = chol(P11),  L21 = P21 L11^{-T},  L22 = chol(P22 - L21 L21^T),
+//   y1 = L11^{-1} b1,  y2 = L22^{-1}(b2 - L21 y1),
+//   x2 = L22^{-T}(y2 + z2),  x1 = L11^{-T}(y1 + z1 - L21^T x2).
+//
+// gfx950 mapping:
+//  * gather: each thread fetches 16-byte pieces of 4 rated rows (BF16 copy,
+//    row stride 128); chunks of 64 ratings are staged feature-major in LDS;
+//  * Gram: the ten lower 32 x 32 tiles on v_mfma_f32_32x32x16_bf16, three,
+//    three, two and two tiles on the four wavefronts; the right-hand side on
+//    v_dot2c_f32_bf16 (threads 0..127, one feature each);
+//  * wavefront 0 factors P11 with the 64-wide row-per-lane Cholesky and does
+//    the forward solve of block 1; wavefront 1 solves for L21 (a row per
+//    lane) and forms L21 L21^T on FP32 matrix cores; wavefront 2 factors the
+//    updated P22 and solves block 2; wavefront 0 finishes block 1.
+//  * a row whose pivot is not finite or not above 64 K 2^-24 max_k P_kk is
+//    not written; it is appended to the FP64 recompute list.
+#include "common.hpp"
+#include "rng.hpp"
+#include "rowsolve.hpp"
+
+namespace bpmf {
+
+namespace {
+
+constexpr int K2 = 128;                       // padded size
+constexpr int H2 = 64;                        // block size
+constexpr int T2 = 256;                       // threads per row
+constexpr int FB2 = K2 / 8;                   // 8-feature blocks
+constexpr int RG2 = T2 / FB2;                 // 4-rating groups per chunk
+constexpr int CH2 = 4 * RG2;                  // ratings per chunk (64)
+constexpr int SB2 = CH2 * 2 + 16;             // bytes per staged feature row
+constexpr int PTRI2 = K2 * (K2 + 1) / 2;      // packed lower triangle of P
+constexpr int STAGE2 = K2 * SB2 / 4;          // staging (floats)
+constexpr int U2 = (PTRI2 + K2) > STAGE2 ? (PTRI2 + K2) : STAGE2;
+constexpr int LTRI2 = H2 * (H2 + 1) / 2 + H2; // packed 64 x 64 triangle + pad
+
+__device__ __forceinline__ int rowoff(int r) { return r * (r + 1) / 2; }
+
+// Lower 32 x 32 tiles (a, b) of the 128 x 128 Gram, by wavefront:
+// wave 0: (0,0) (1,0) (1,1); wave 1: (2,0) (2,1) (2,2); wave 2: (3,0) (3,1);
+// wave 3: (3,2) (3,3).  `wave` is uniform, so these are scalar selects.
+__device__ __forceinline__ void tile_of(int wave, int t, int &a, int &b)
+{
+    a = wave == 0 ? (t == 0 ? 0 : 1) : (wave == 1 ? 2 : 3);
+    b = wave == 0 ? (t == 2 ? 1 : 0) : (wave == 3 ? 2 + t : t);
+}
+
+__global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(3, 3))) void rows_mixed128_kernel(
+    SideArgs sa, int K, float alpha, float rbar, HyperDev hyp, DrawSrc draws, int32_t *fb_list,
+    DevState *state, int side)
+{
+    __shared__ __attribute__((aligned(16))) float u[U2];     // staging, then P (packed), then L11 / L21 in place
+    __shared__ __attribute__((aligned(16))) float l22[LTRI2]; // L22 (packed)
+    __shared__ __attribute__((aligned(16))) float pb0[H2 * 12], pb2[H2 * 12];
+    __shared__ __attribute__((aligned(16))) float bvec[K2], zvec[K2];
+    __shared__ __attribute__((aligned(16))) float y1[H2], b2[H2], x2v[H2], inv11[H2], inv22[H2], yb2[H2],
+        xb2[H2], xb0[H2];
+    __shared__ __attribute__((aligned(16))) uint32_t rvp[CH2];
+    __shared__ float red[4];
+    __shared__ int fails[2];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t slot = blockIdx.x;
+    const int row = sa.order ? sa.order[slot] : (int)slot;
+    const int64_t s0 = sa.ptr[row], s1 = sa.ptr[row + 1];
+    const int64_t nnz = s1 - s0;
+    const int32_t *idx = sa.idx + s0;
+    const float *vals = (const float *)sa.val + s0;
+    const uint16_t *src = sa.other_bf16;
+    const int32_t sentinel = (int32_t)sa.n_other;
+
+    // ---------------- Gram (matrix cores) and right-hand side ----------------
+    const int ntile = wave < 2 ? 3 : 2;
+    floatx16 acc[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
+    float bacc = 0.0f;
+    char *stage = (char *)u;
+    const int fb = tid / RG2, rg = tid % RG2;
+    auto load_idx = [&](int64_t c0, int *j) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t n = c0 + rg * 4 + q;
+            j[q] = idx[n < nnz ? n : nnz - 1];
+        }
+    };
+    auto load_rows = [&](int64_t c0, const int *j, uint4 *d, float *v) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t n = c0 + rg * 4 + q;
+            const int jj = blend_idx(n < nnz, j[q], sentinel);
+            d[q] = *(const uint4 *)(src + (int64_t)jj * K2 + fb * 8);
+            v[q] = vals[n < nnz ? n : nnz - 1];
+        }
+    };
+    auto stage_chunk = [&](int64_t c0, const uint4 *d, const float *vraw) {
+        if (fb == 0) {
+            uint32_t hi[4], lo[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t n = c0 + rg * 4 + q;
+                const float v = (vraw[q] - rbar) * (n < nnz ? 1.0f : 0.0f);
+                hi[q] = f32_to_bf16_rne(v);
+                lo[q] = f32_to_bf16_rne(v - bf16_to_f32((uint16_t)hi[q]));
+            }
+            *(uint2 *)(rvp + rg * 2) = make_uint2(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16));
+            *(uint2 *)(rvp + CH2 / 2 + rg * 2) = make_uint2(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16));
+        }
+        const uint32_t w0[4] = {d[0].x, d[0].y, d[0].z, d[0].w};
+        const uint32_t w1[4] = {d[1].x, d[1].y, d[1].z, d[1].w};
+        const uint32_t w2[4] = {d[2].x, d[2].y, d[2].z, d[2].w};
+        const uint32_t w3[4] = {d[3].x, d[3].y, d[3].z, d[3].w};
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int f = fb * 8 + 2 * w;
+            uint2 lo, hi;
+            lo.x = (w0[w] & 0xffffu) | (w1[w] << 16);
+            lo.y = (w2[w] & 0xffffu) | (w3[w] << 16);
+            hi.x = (w0[w] >> 16) | (w1[w] & 0xffff0000u);
+            hi.y = (w2[w] >> 16) | (w3[w] & 0xffff0000u);
+            *(uint2 *)(stage + f * SB2 + rg * 8) = lo;
+            *(uint2 *)(stage + (f + 1) * SB2 + rg * 8) = hi;
+        }
+    };
+    auto multiply_chunk = [&]() {
+#pragma unroll
+        for (int ks = 0; ks < CH2 / 16; ++ks) {
+            const int off = (ks * 16 + (lane >> 5) * 8) * 2;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                if (t < ntile) {
+                    int ta, tb;
+                    tile_of(wave, t, ta, tb);
+                    const bf16x8_t Fa = *(const bf16x8_t *)(stage + (32 * ta + (lane & 31)) * SB2 + off);
+                    const bf16x8_t Fb = *(const bf16x8_t *)(stage + (32 * tb + (lane & 31)) * SB2 + off);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Fa, Fb, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        if (tid < K2) {
+            const uint32_t *sp = (const uint32_t *)(stage + tid * SB2);
+#pragma unroll
+            for (int p = 0; p < CH2 / 2; ++p) {
+                bf16x2_t x, yh, yl;
+                const uint32_t sv = sp[p], hv = rvp[p], lv = rvp[CH2 / 2 + p];
+                __builtin_memcpy(&x, &sv, 4);
+                __builtin_memcpy(&yh, &hv, 4);
+                __builtin_memcpy(&yl, &lv, 4);
+                bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yh, bacc, false);
+                bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yl, bacc, false);
+            }
+        }
+    };
+    {
+        int j[4];
+        uint4 d[4];
+        float v[4];
+        if (nnz > 0) {
+            load_idx(0, j);
+            load_rows(0, j, d, v);
+            if (CH2 < nnz) load_idx(CH2, j);
+        }
+        for (int64_t c0 = 0; c0 < nnz; c0 += CH2) {
+            stage_chunk(c0, d, v);
+            if (c0 + CH2 < nnz) {
+                load_rows(c0 + CH2, j, d, v);
+                if (c0 + 2 * CH2 < nnz) load_idx(c0 + 2 * CH2, j);
+            }
+            __syncthreads();
+            multiply_chunk();
+            __syncthreads();
+        }
+    }
+
+    // ---------------- P = Lambda + alpha G, b, z ----------------
+    float *P = u;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (t < ntile) {
+            int ta, tb;
+            tile_of(wave, t, ta, tb);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 32 * ta + 8 * j + 4 * (lane >> 5) + i;
+                    const int c = 32 * tb + (lane & 31);
+                    const int e = rowoff(r) + c;  // < PTRI2 + K2 for every lane
+                    const float val = fmaf(alpha, acc[t][4 * j + i], hyp.Lambda_tri[e]);
+                    if (c <= r) P[e] = val;
+                }
+        }
+    }
+    if (tid < K2) {
+        const float lmu = hyp.Lmu_f[tid < K ? tid : 0];
+        bvec[tid] = tid < K ? fmaf(alpha, bacc, lmu) : 0.0f;
+    }
+    if (draws.tape_rows) {
+        if (tid < K2) zvec[tid] = tid < K ? (float)draws.tape_rows[(int64_t)row * K + (tid < K ? tid : 0)] : 0.0f;
+    } else if (tid < K2 / 2) {
+        const uint32_t h = half_sweep_index(draws);
+        float z0, z1;
+        box_muller_f32(philox4x32_10(ctr4((uint32_t)tid, (uint32_t)row, h, 0u), draws.seed), z0, z1);
+        zvec[2 * tid] = 2 * tid < K ? z0 : 0.0f;
+        zvec[2 * tid + 1] = 2 * tid + 1 < K ? z1 : 0.0f;
+    }
+    __syncthreads();
+    // tau = 64 K 2^-24 max_{k<K} P_kk
+    if (wave < 2) {
+        const int k = tid;
+        float dg = k < K ? P[rowoff(k) + k] : 0.0f;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) dg = fmaxf(dg, __shfl_xor(dg, o));
+        if (lane == 0) red[wave] = dg;
+    }
+    __syncthreads();
+    const float tau = 64.0f * (float)K * 0x1.0p-24f * fmaxf(red[0], red[1]);
+
+    // ---------------- block 1: L11, y1 (wavefront 0); P21 rows (wavefront 1) ----------------
+    float A[H2];
+    if (wave == 0) {
+#pragma unroll
+        for (int c = 0; c < H2; ++c) A[c] = P[rowoff(lane) + c];
+        WaveSync::sync();
+        chol_factor<H2, WaveSync>(A, inv11, pb0);
+        const float iv = inv11[lane];
+        const bool f0 = chol_pivots_fail(iv, lane, K < H2 ? K : H2, tau);
+        if (lane == 0) fails[0] = f0 ? 1 : 0;
+        forward_sub<H2, WaveSync>(A, iv, bvec[lane], y1);
+        store_rows<H2>(A, P);  // L11 over P11
+    } else if (wave == 1) {
+#pragma unroll
+        for (int c = 0; c < H2; ++c) A[c] = P[rowoff(H2 + lane) + c];
+    }
+    __syncthreads();
+
+    // ---------------- L21, b2 - L21 y1, P22 - L21 L21^T (wavefront 1) ----------------
+    if (wave == 1) {
+        // row r of L21 solves x L11^T = P21 row r: x_k = (p_k - sum_{m<k} L11_km x_m) / L11_kk
+#pragma unroll
+        for (int k = 0; k < H2; ++k) {
+            const float *lk = P + rowoff(k);
+            float s0 = A[k], s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+#pragma unroll
+            for (int m = 0; m + 3 < k; m += 4) {
+                s0 = fmaf(-lk[m], A[m], s0);
+                s1 = fmaf(-lk[m + 1], A[m + 1], s1);
+                s2 = fmaf(-lk[m + 2], A[m + 2], s2);
+                s3 = fmaf(-lk[m + 3], A[m + 3], s3);
+            }
+#pragma unroll
+            for (int m = k & ~3; m < k; ++m) s0 = fmaf(-lk[m], A[m], s0);
+            A[k] = ((s0 + s1) + (s2 + s3)) * inv11[k];
+        }
+        // b2 - L21 y1
+        float t = bvec[H2 + lane];
+#pragma unroll
+        for (int k = 0; k < H2; ++k) t = fmaf(-A[k], y1[k], t);
+        b2[lane] = t;
+        // L21 over P21 (read again by the block-1 back substitution)
+#pragma unroll
+        for (int c = 0; c < H2; ++c) P[rowoff(H2 + lane) + c] = A[c];
+        // C = L21 L21^T in three 32 x 32 tiles (rows 0-31 "lo", 32-63 "hi" of
+        // L21), 32 rank-2 steps of v_mfma_f32_32x32x2_f32 each.  One
+        // permlane32 swap of columns 2kk and 2kk+1 gives both operands: the
+        // first result has the lo rows' two columns in the two lane halves,
+        // the second the hi rows'.
+        floatx16 c00 = {}, c10 = {}, c11 = {};
+#pragma unroll
+        for (int kk = 0; kk < H2 / 2; ++kk) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[2 * kk]), __float_as_uint(A[2 * kk + 1]),
+                                                             false, false);
+            const float xlo = __uint_as_float(sw[0]), xhi = __uint_as_float(sw[1]);
+            c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(xlo, xlo, c00, 0, 0, 0);
+            c10 = __builtin_amdgcn_mfma_f32_32x32x2f32(xhi, xlo, c10, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(xhi, xhi, c11, 0, 0, 0);
+        }
+        // result element v = 4j + i of lane l is C[8j + 4(l / 32) + i][l % 32]
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 8 * j + 4 * (lane >> 5) + i, n = lane & 31;
+                const int e00 = rowoff(H2 + m) + H2 + n;
+                const int e10 = rowoff(H2 + 32 + m) + H2 + n;
+                const int e11 = rowoff(H2 + 32 + m) + H2 + 32 + n;
+                if (n <= m) P[e00] -= c00[4 * j + i];
+                P[e10] -= c10[4 * j + i];
+                if (n <= m) P[e11] -= c11[4 * j + i];
+            }
+    }
+    __syncthreads();
+
+    // ---------------- block 2: L22, y2, x2 (wavefront 2) ----------------
+    if (wave == 2) {
+#pragma unroll
+        for (int c = 0; c < H2; ++c) A[c] = P[rowoff(H2 + lane) + H2 + c];
+        WaveSync::sync();
+        chol_factor<H2, WaveSync>(A, inv22, pb2);
+        const float iv = inv22[lane];
+        const bool f2 = chol_pivots_fail(iv, lane, K - H2, tau);
+        if (lane == 0) fails[1] = f2 ? 1 : 0;
+        const float y = forward_sub<H2, WaveSync>(A, iv, b2[lane], yb2);
+        store_rows<H2>(A, l22);
+        WaveSync::sync();
+        x2v[lane] = backward_sub<H2, WaveSync>(l22, iv, y + zvec[H2 + lane], xb2);
+    }
+    __syncthreads();
+
+    // ---------------- block 1: x1 = L11^{-T}(y1 + z1 - L21^T x2) (wavefront 0) ----------------
+    const bool fail = (fails[0] | fails[1]) != 0;
+    if (wave == 0) {
+        float w = y1[lane] + zvec[lane];
+#pragma unroll
+        for (int r = 0; r < H2; ++r) w = fmaf(-P[rowoff(H2 + r) + lane], x2v[r], w);
+        const float x1 = backward_sub<H2, WaveSync>(P, inv11[lane], w, xb0);
+        if (!fail) {
+            float *X = (float *)sa.X;
+            if (lane < K) X[(int64_t)row * K + lane] = x1;
+            if (sa.X_bf16) sa.X_bf16[(int64_t)row * K2 + lane] = lane < K ? f32_to_bf16_rne(x1) : (uint16_t)0;
+        }
+    } else if (wave == 2 && !fail) {
+        const float x2 = x2v[lane];
+        float *X = (float *)sa.X;
+        if (H2 + lane < K) X[(int64_t)row * K + H2 + lane] = x2;
+        if (sa.X_bf16) sa.X_bf16[(int64_t)row * K2 + H2 + lane] = H2 + lane < K ? f32_to_bf16_rne(x2) : (uint16_t)0;
+    }
+    if (fail && tid == 0) {
+        const int pos = atomicAdd(&state->fb_count[side], 1);
+        fb_list[pos] = row;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_rows_mixed128(const SideArgs &a, int K, double alpha, double rbar, HyperDev hyp,
+                                DrawSrc draws, int32_t *fb_list, DevState *state, hipStream_t s)
+{
+    if (a.n_rows <= 0) return hipSuccess;
+    if (K <= 64 || K > 128 || !a.other_bf16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rows_mixed128_kernel, dim3((unsigned)a.n_rows), dim3(T2), 0, s, a, K, (float)alpha,
+                       (float)rbar, hyp, draws, fb_list, state, draws.side);
+    return hipGetLastError();
+}
+
+}  // namespace bpmf

@@ -478,7 +478,7 @@ hipError_t prepare_nw()
 
 hipError_t launch_lambda_tri(HyperDev hyp, int K, int KP, hipStream_t s)
 {
-    if (K > 64) return hipSuccess;
+    if (K > 128) return hipSuccess;
     hipLaunchKernelGGL(lambda_tri_kernel, dim3(1), dim3(256), 0, s, hyp, K, KP);
     return hipGetLastError();
 }

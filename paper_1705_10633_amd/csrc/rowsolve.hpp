@@ -290,47 +290,41 @@ __device__ __forceinline__ void syrk_trailing(float *A)
         }
 }
 
-// Factor P (packed in `tri`) and return x = L^{-T}(L^{-1} b + z) on lane
-// ri = lane % KP, where lane ri holds b_ri and z_ri.  `fail` is set (uniformly
-// across the wave) when a pivot is not finite or not above
-// 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with L; `aux` holds 3 KP floats.
+// Synchronisation inside a factorisation or solve: BlockSync when the
+// workgroup is the one wavefront doing the work; WaveSync when other
+// wavefronts of the workgroup are busy elsewhere (LDS operations of one
+// wavefront are processed in order, so only the compiler must keep the
+// program order).
+struct BlockSync {
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+struct WaveSync {
+    static __device__ __forceinline__ void sync() { __asm__ volatile("" ::: "memory"); }
+};
+
+// Factor the KP x KP matrix whose row ri = lane % KP is in A (registers):
+// afterwards A holds row ri of L (lower, L L^T = P) and invbuf[k] = 1/L_kk.
+// `pbuf` is KP x 12 floats of LDS scratch.
 //
-// Lane ri keeps row ri of P in registers.  The factorisation runs in panels
-// of 8 columns: inside a panel, column k is scaled by 1/sqrt(P_kk) (lane k
-// thereby holds L_kk) and the later panel columns are updated with values
-// read across lanes with readlane; then every lane publishes its 8 panel
-// entries through LDS once and applies the rank-8 update to its trailing
-// columns.  Entries right of the diagonal are updated too but never read,
-// and a lane whose solution component is final keeps computing on values
-// nobody reads, so the loops need no lane masks.
-template <int KP>
-__device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float bb, float z,
-                                            bool &fail)
+// The factorisation runs in panels of 8 columns: inside a panel, column k is
+// scaled by 1/sqrt(P_kk) (lane k thereby holds L_kk) and the later panel
+// columns are updated with values read across lanes with readlane; then every
+// lane publishes its 8 panel entries through LDS once and applies the rank-8
+// update to its trailing columns.  Entries right of the diagonal are updated
+// too but never read, so the loops need no lane masks.  An unusable pivot
+// gives a NaN, infinite or zero 1/sqrt, caught by chol_pivots_fail.
+template <int KP, class Sync = BlockSync>
+__device__ __forceinline__ void chol_factor(float (&A)[KP], float *invbuf, float *pbuf)
 {
     constexpr int PW = 8;
-    const int lane = threadIdx.x & 63;
-    const int ri = lane % KP;
-    float *invbuf = aux, *ybuf = aux + KP, *xbuf = aux + 2 * KP;
-    float *pbuf = tri;  // KP x 12 panel broadcast; P has been read into registers by then
     // pbuf rows are 12 floats apart, so 16 consecutive lanes cover all 64
     // LDS banks with their 16-byte writes
     constexpr int PS = 12;
-    const int rbase = ri * (ri + 1) / 2;
-    float A[KP];
-#pragma unroll
-    for (int c = 0; c < KP; ++c) A[c] = tri[rbase + c];
-    float dg = (ri < K) ? tri[rbase + ri] : 0.0f;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) dg = fmaxf(dg, __shfl_xor(dg, o));
-    const float tau = 64.0f * (float)K * 0x1.0p-24f * dg;
-    __syncthreads();
-
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int c0 = 0; c0 < KP; c0 += PW) {
 #pragma unroll
         for (int k = c0; k < c0 + PW; ++k) {
-            // an unusable pivot gives a NaN, infinite or zero 1/sqrt and is
-            // caught by the check after the loop
             const float inv = __builtin_amdgcn_rsqf(readlane_f(A[k], k));
             A[k] *= inv;
             invbuf[k] = inv;
@@ -347,7 +341,7 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
                 *(float4 *)(pbuf + lane * PS) = make_float4(A[c0], A[c0 + 1], A[c0 + 2], A[c0 + 3]);
                 *(float4 *)(pbuf + lane * PS + 4) = make_float4(A[c0 + 4], A[c0 + 5], A[c0 + 6], A[c0 + 7]);
             }
-            __syncthreads();
+            Sync::sync();
 #pragma unroll
             for (int j = c0 + PW; j < jend; ++j) {
                 const float4 p0 = *(const float4 *)(pbuf + j * PS);
@@ -363,44 +357,97 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
                 t = fmaf(-A[c0 + 7], p1.w, t);
                 A[j] = t;
             }
-            __syncthreads();
+            Sync::sync();
         }
         if constexpr (KP == 64)
             if (c0 + PW == HALF) syrk_trailing(A);
     }
-    {
-        // pivot d_k fails when it is not finite or d_k <= tau, i.e. when
-        // 1/sqrt(d_k) is not a positive finite number with tau / d_k < 1;
-        // the identity pivots of the padding are not checked
-        const float ik = invbuf[ri];
-        const bool bk = (ri < K) && !((ik > 0.0f) && (ik * ik * tau < 1.0f));
-        fail = __ballot(bk) != 0;
-    }
-    const float invd = invbuf[ri];
-    // y = L^{-1} b: y_k is taken from lane k before later steps overwrite it
+}
+
+// A pivot d_k (k < kmax) fails when it is not finite or d_k <= tau, i.e. when
+// 1/sqrt(d_k) is not a positive finite number with tau / d_k < 1; the
+// identity pivots of the padding (k >= kmax) are not checked.  Uniform.
+__device__ __forceinline__ bool chol_pivots_fail(float inv_own, int ri, int kmax, float tau)
+{
+    const bool bk = (ri < kmax) && !((inv_own > 0.0f) && (inv_own * inv_own * tau < 1.0f));
+    return __ballot(bk) != 0;
+}
+
+// y = L^{-1} b with row ri of L in A and b_ri in bb; returns y_ri.  y_k is
+// taken from lane k before later steps overwrite it; ybuf holds KP floats.
+template <int KP, class Sync = BlockSync>
+__device__ __forceinline__ float forward_sub(const float (&A)[KP], float invd, float bb, float *ybuf)
+{
+    const int ri = (threadIdx.x & 63) % KP;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         const float yk = readlane_f(bb * invd, k);
         ybuf[k] = yk;
         bb = fmaf(-A[k], yk, bb);
     }
-    // rows of L back to LDS for the transposed solve (lower triangle only:
-    // a lane's entries right of its diagonal would land in other rows' slots)
+    Sync::sync();
+    return ybuf[ri];
+}
+
+// Rows of L (lower triangle only: a lane's entries right of its diagonal
+// would land in other rows' slots) into the packed triangle `tri`.
+template <int KP>
+__device__ __forceinline__ void store_rows(const float (&A)[KP], float *tri)
+{
+    const int lane = threadIdx.x & 63;
+    const int ri = lane % KP;
+    const int rbase = ri * (ri + 1) / 2;
     if (lane < KP) {
 #pragma unroll
         for (int c = 0; c < KP; ++c)
             if (c <= ri) tri[rbase + c] = A[c];
     }
-    __syncthreads();
-    float w = ybuf[ri] + z;
+}
+
+// x = L^{-T} w with L packed in `tri` and w_ri in w; returns x_ri.  xbuf
+// holds KP floats.
+template <int KP, class Sync = BlockSync>
+__device__ __forceinline__ float backward_sub(const float *tri, float invd, float w, float *xbuf)
+{
+    const int ri = (threadIdx.x & 63) % KP;
 #pragma unroll
     for (int k = KP - 1; k >= 0; --k) {
         const float xk = readlane_f(w * invd, k);
         xbuf[k] = xk;
         w = fmaf(-tri[k * (k + 1) / 2 + ri], xk, w);
     }
+    Sync::sync();
+    return xbuf[ri];
+}
+
+// Factor P (packed in `tri`) and return x = L^{-T}(L^{-1} b + z) on lane
+// ri = lane % KP, where lane ri holds b_ri and z_ri.  `fail` is set (uniformly
+// across the wave) when a pivot is not finite or not above
+// 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with L; `aux` holds 3 KP floats.
+// Lane ri keeps row ri of P in registers through chol_factor.
+template <int KP>
+__device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float bb, float z,
+                                            bool &fail)
+{
+    const int lane = threadIdx.x & 63;
+    const int ri = lane % KP;
+    float *invbuf = aux, *ybuf = aux + KP, *xbuf = aux + 2 * KP;
+    const int rbase = ri * (ri + 1) / 2;
+    float A[KP];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) A[c] = tri[rbase + c];
+    float dg = (ri < K) ? tri[rbase + ri] : 0.0f;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) dg = fmaxf(dg, __shfl_xor(dg, o));
+    const float tau = 64.0f * (float)K * 0x1.0p-24f * dg;
     __syncthreads();
-    const float x = xbuf[ri];
+    chol_factor<KP>(A, invbuf, tri);  // P is in registers: tri serves as the panel buffer
+    fail = chol_pivots_fail(invbuf[ri], ri, K, tau);
+    const float invd = invbuf[ri];
+    const float y = forward_sub<KP>(A, invd, bb, ybuf);
+    store_rows<KP>(A, tri);
+    __syncthreads();
+    const float x = backward_sub<KP>(tri, invd, y + z, xbuf);
     __syncthreads();
     return x;
 }

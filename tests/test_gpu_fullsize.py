@@ -2,8 +2,10 @@
 
 One sweep of the MovieLens-shaped problem (138,493 x 26,744, 20M ratings,
 K = 64, BF16 gathers and Gram, FP32 Cholesky, device Philox draws, HIP-graph
-replay) and of the ChEMBL-shaped one (483,500 x 5,775, 1.02M ratings, K = 32,
-FP32), both from the same library calls the benchmark makes. The oracle
+replay), of the ChEMBL-shaped one (483,500 x 5,775, 1.02M ratings, K = 32,
+FP32) and of the Netflix-shaped one (480,189 x 17,770, 100M ratings, K = 128,
+BF16, the blocked four-wavefront kernel), from the same library calls the
+benchmark makes. The oracle
 cannot redo a whole sweep in seconds, so it recomputes
 
   * both Normal-Wishart steps (Alg. 1, hyper-parameter draws) from the same
@@ -136,3 +138,8 @@ def test_movielens_shaped_bf16_sampled_parity():
 def test_chembl_shaped_fp32_sampled_parity():
     prob = synth.chembl_like(burnin=0)
     _check_full_size(prob, "fp32")
+
+
+def test_netflix_shaped_bf16_sampled_parity():
+    prob = synth.netflix_like(burnin=0)
+    _check_full_size(prob, "bf16", n_uniform=600, n_ends=50)

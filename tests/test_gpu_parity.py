@@ -122,9 +122,11 @@ def _one_sweep_from_f32_state(prob, precision, tape):
 MIXED_TOL = {"fp32": (1e-5, 1e-3), "bf16": (1e-2, 1e-1)}
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-@pytest.mark.parametrize("K", [10, 32, 64])
+@pytest.mark.parametrize("precision,K", [(p, k) for p in ("fp32", "bf16") for k in (10, 32, 64)]
+                         + [("bf16", 100), ("bf16", 128), ("fp32", 100)])
 def test_mixed_one_sweep_error(precision, K):
+    """K <= 64: one wavefront per row; BF16 with 64 < K <= 128: the blocked
+    four-wavefront kernel; FP32 with K > 64: FP64 row arithmetic."""
     prob = synth.uniform_planted(M=600, N=300, K=K, nnz=30000, seed=K, n_sweeps=1, burnin=0)
     tape = tape_for(prob, 1, seed=K + 1)
     s, ref = _one_sweep_from_f32_state(prob, precision, tape)
