@@ -51,11 +51,12 @@ class ServerStats(C.Structure):
                 ("max_batch_bytes", I64), ("stream_capacity", I64)]
 
 
-TIMING_CLASSES = ("stats", "hyper", "rows_users", "rows_movies", "fp64_recompute", "predict", "counter")
+TIMING_CLASSES = ("stats", "hyper", "rows_users", "rows_movies", "fp64_recompute", "predict", "counter",
+                  "rows_rank1", "rows_heavy")
 
 
 class Timing(C.Structure):
-    _fields_ = [("ms", F64 * 7), ("launches", I64 * 7)]
+    _fields_ = [("ms", F64 * len(TIMING_CLASSES)), ("launches", I64 * len(TIMING_CLASSES))]
 
 
 class BpmfError(RuntimeError):

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbpmf.so")
-SOURCES = ["bpmf_host.hip", "kernels_f64.hip", "kernels_nw.hip", "kernels_mixed.hip", "kernels_mixed128.hip",
+SOURCES = ["bpmf_host.hip", "kernels_f64.hip", "kernels_nw.hip", "kernels_mixed.hip", "kernels_mixed128.hip", "kernels_rank1.hip",
            "kernels_foldin.hip", "serving.hip"]
 ARCH = "gfx950"
 

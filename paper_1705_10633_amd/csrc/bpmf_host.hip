@@ -65,7 +65,7 @@ struct WsLayout {
 };
 
 struct Offsets {
-    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], nwd[2], mu0, w0inv,
+    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], lchol[2], nwd[2], mu0, w0inv,
         order[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
@@ -78,6 +78,15 @@ static int padded_k(int K) { return K <= 32 ? 32 : (K <= 64 ? 64 : 128); }
 static bool mixed_supported(int K, int precision)
 {
     return K <= 64 || (precision == BPMF_BF16 && K <= 128);
+}
+
+// Rows with at most this many ratings take the rank-one kernel (K <= 64): m
+// updates cost about m K steps of a few instructions per lane, against a
+// Cholesky of K steps with up to K instructions each plus the Gram pipeline.
+static int64_t rank1_limit(int K)
+{
+    const int64_t lim = K <= 32 ? 3 : 2;
+    return std::min<int64_t>(lim, rank1_max_ratings());
 }
 
 static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_test)
@@ -100,6 +109,7 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
         o.lamf[s] = w.add(sizeof(float) * K * K);
         o.lmuf[s] = w.add(sizeof(float) * K);
         o.lamt[s] = w.add(sizeof(float) * (size_t)padded_k(K) * (padded_k(K) + 3) / 2);
+        o.lchol[s] = w.add((mk && K <= 64) ? sizeof(float) * (size_t)padded_k(K) * (padded_k(K) + 4) : 0);
         o.nwd[s] = w.add(sizeof(double) * (size_t)(2 * K + K * (K - 1) / 2));
         o.order[s] = w.add(sizeof(int32_t) * n[s]);
         o.fblist[s] = w.add(mk ? sizeof(int32_t) * n[s] : 0);
@@ -129,6 +139,11 @@ struct bpmf_ctx {
     DevState *state;
     HyperDev hyp[2];
     int n_chunks[2];
+    // tails of the row order: rows for the rank-one kernels (n_small), of
+    // which the last n_tiny (at most one rating, K <= 32) take the one-lane kernel
+    int64_t n_small[2] = {0, 0}, n_tiny[2] = {0, 0};
+    // head of the row order: rows for the multi-wavefront kernel (K <= 64)
+    int64_t n_heavy[2] = {0, 0};
     int64_t n_test;
     const int32_t *test_rows, *test_cols;
     hipGraph_t graph = nullptr;
@@ -348,6 +363,8 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         c->hyp[sd].Lambda_f = c->at<float>(off.lamf[sd]);
         c->hyp[sd].Lmu_f = c->at<float>(off.lmuf[sd]);
         c->hyp[sd].Lambda_tri = c->at<float>(off.lamt[sd]);
+        c->hyp[sd].Lchol = (mixed_supported(K, p->precision) && p->precision != BPMF_FP64 && K <= 64)
+                               ? c->at<float>(off.lchol[sd]) : nullptr;
     }
     auto bail = [&](bpmf_status e) { delete c; return e; };
 #define HIP_OK_C(expr)                                                                      \
@@ -388,6 +405,30 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         });
         HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.order[sd]), ord.data(), sizeof(int32_t) * n[sd], hipMemcpyHostToDevice, s));
         HIP_OK_C(hipStreamSynchronize(s));
+        if (c->hyp[sd].Lchol) {
+            const int64_t lim = rank1_limit(K);
+            int64_t m = 0;
+            int64_t t = 0;
+            while (m < n[sd] && pp[ord[n[sd] - 1 - m] + 1] - pp[ord[n[sd] - 1 - m]] <= lim) {
+                if (pp[ord[n[sd] - 1 - m] + 1] - pp[ord[n[sd] - 1 - m]] <= 1) ++t;
+                ++m;
+            }
+            // a short tail finishes inside the full kernel's launch anyway;
+            // a separate launch pays off once it is a sizeable share of the rows
+            if (m >= 16384 || 16 * m >= n[sd]) {
+                c->n_small[sd] = m;
+                c->n_tiny[sd] = K <= 32 ? t : 0;
+            }
+            // the multi-wavefront launch runs before the one-wavefront launch;
+            // it pays off when the heavy rows hold a sizeable share of the
+            // ratings (otherwise they finish inside the one-wavefront launch)
+            int64_t hv = 0, hnnz = 0;
+            while (hv < n[sd] - m && pp[ord[hv] + 1] - pp[ord[hv]] >= heavy_min_ratings()) {
+                hnnz += pp[ord[hv] + 1] - pp[ord[hv]];
+                ++hv;
+            }
+            c->n_heavy[sd] = 10 * hnnz >= R->nnz ? hv : 0;
+        }
     }
     // held-out pairs sorted by user (then movie) so that predictions reuse rows
     if (n_test > 0) {
@@ -565,14 +606,37 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
         time_end(c, 2 + side, t0, s);
         return BPMF_OK;
     }
-    t0 = time_begin(c, s);
-    if (K <= 64)
-        HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d,
-                                 c->at<int32_t>(c->off.fblist[side]), c->state, s));
-    else
-        HIP_OK(launch_rows_mixed128(a, K, c->alpha, c->rbar, c->hyp[side], d, c->at<int32_t>(c->off.fblist[side]),
-                                    c->state, s));
-    time_end(c, 2 + side, t0, s);
+    int32_t *fbl = c->at<int32_t>(c->off.fblist[side]);
+    if (K <= 64) {
+        // order slots: [0, nh) heavy rows, [nh, n - ns) one wavefront per row,
+        // [n - ns, n - nt) rank-one updates, [n - nt, n) one lane per row
+        const int64_t nh = c->n_heavy[side], ns = c->n_small[side], nt = c->n_tiny[side];
+        if (nh > 0) {
+            SideArgs ah = a;
+            ah.n_rows = nh;
+            t0 = time_begin(c, s);
+            HIP_OK(launch_rows_heavy(ah, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, s));
+            time_end(c, 8, t0, s);
+        }
+        SideArgs ab = a;
+        ab.order = a.order + nh;
+        ab.n_rows = n - ns - nh;
+        t0 = time_begin(c, s);
+        HIP_OK(launch_rows_mixed(ab, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, s));
+        time_end(c, 2 + side, t0, s);
+        if (ns > 0) {
+            t0 = time_begin(c, s);
+            HIP_OK(launch_rows_rank1(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state,
+                                     n - ns, n - nt, R.nnz, s));
+            HIP_OK(launch_rows_tiny(a, K, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, n - nt, n,
+                                    R.nnz, s));
+            time_end(c, 7, t0, s);
+        }
+    } else {
+        t0 = time_begin(c, s);
+        HIP_OK(launch_rows_mixed128(a, K, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, s));
+        time_end(c, 2 + side, t0, s);
+    }
     t0 = time_begin(c, s);
     HIP_OK(launch_rows_f64(a, K, c->alpha, c->rbar, c->hyp[side], d, c->at<int32_t>(c->off.fblist[side]),
                            &c->state->fb_count[side], n, 1, c->state, s));

@@ -46,6 +46,11 @@ struct HyperDev {
     // FP32 Lambda as the mixed row kernel's packed lower triangle of the
     // padded size KP (row r at r (r + 1) / 2, identity in the padding), KP (KP + 3) / 2 floats
     float *Lambda_tri;
+    // chol(Lambda) in FP32 for the rank-one row paths (K <= 64), or NULL:
+    // KP x KP row-major (lower; identity in the padding), then KP floats each
+    // of 1 / L_ii, L^T mu (= L^{-1} Lambda mu), Lambda_ii (0 in the padding)
+    // and 1 / 0 flags of the live components
+    float *Lchol;
 };
 
 // One half-sweep: rows of one side against the other side's factors.
@@ -127,6 +132,22 @@ hipError_t launch_rows_mixed128(const SideArgs &a, int K, double alpha, double r
 hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double alpha,
                              double rbar, HyperDev hyp, DrawSrc draws, int32_t *fb_list,
                              DevState *state, hipStream_t s);
+// The first a.n_rows rows of a.order, each with at least heavy_min_ratings()
+// ratings: gathers and Gram split over several wavefronts per row (K <= 64).
+int heavy_min_ratings();
+hipError_t launch_rows_heavy(const SideArgs &a, int K, int KP, int bf16, double alpha, double rbar, HyperDev hyp,
+                             DrawSrc draws, int32_t *fb_list, DevState *state, hipStream_t s);
+// Rows in order slots [slot0, slot1), each with at most rank1_max_ratings()
+// ratings, by rank-one updates of chol(Lambda) (K <= 64, hyp.Lchol set).
+int rank1_max_ratings();
+// Rows in order slots [slot0, slot1) with at most one rating, K <= 32: one
+// lane per row, closed-form factor of I + p p^T.
+hipError_t launch_rows_tiny(const SideArgs &a, int K, int bf16, double alpha, double rbar, HyperDev hyp,
+                            DrawSrc draws, int32_t *fb_list, DevState *state, int64_t slot0, int64_t slot1,
+                            int64_t nnz, hipStream_t s);
+hipError_t launch_rows_rank1(const SideArgs &a, int K, int KP, int bf16, double alpha, double rbar, HyperDev hyp,
+                             DrawSrc draws, int32_t *fb_list, DevState *state, int64_t slot0, int64_t slot1,
+                             int64_t nnz, hipStream_t s);
 hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, double rbar,
                           int64_t n, const int32_t *rows, const int32_t *cols, double *out,
                           double *accum, const DevState *state, int burnin, hipStream_t s);

@@ -444,9 +444,28 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
             }
             if (c <= a && a < KPm)
                 hyp.Lambda_tri[a * (a + 1) / 2 + c] = (a < K && c < K) ? (float)acc[cc] : (a == c ? 1.0f : 0.0f);
+            // T is chol(Lambda): lower with a positive diagonal, Lambda = T T^T
+            if (hyp.Lchol && a < KPm && c < KPm)
+                hyp.Lchol[a * KPm + c] =
+                    (a < K && c < K) ? (c <= a ? (float)Tm[a * NCS + c] : 0.0f) : (a == c ? 1.0f : 0.0f);
             lmu = fma(acc[cc], mul[c], lmu);
         }
         lpart[wave * NWK + a] = lmu;
+    }
+    if (hyp.Lchol && wave == 1) {
+        // for the rank-one row paths: 1 / T_ll, T^T mu, Lambda_ll and live-component flags
+        const int KPm = K <= 32 ? 32 : 64;
+        if (lane < KPm) {
+            const bool in = lane < K;
+            double tmu = 0.0, ll = 0.0;
+            for (int k = lane; k < K; ++k) tmu = fma(Tm[k * NCS + lane], mul[k], tmu);
+            for (int m = 0; m <= lane && m < K; ++m) ll = fma(Tm[lane * NCS + m], Tm[lane * NCS + m], ll);
+            float *ext = hyp.Lchol + KPm * KPm;
+            ext[lane] = in ? (float)(1.0 / Tm[lane * NCS + lane]) : 1.0f;
+            ext[KPm + lane] = in ? (float)tmu : 0.0f;
+            ext[2 * KPm + lane] = in ? (float)ll : 0.0f;
+            ext[3 * KPm + lane] = in ? 1.0f : 0.0f;
+        }
     }
     __syncthreads();
     if (wave == 0 && lane < K) {

@@ -38,6 +38,18 @@ __device__ __forceinline__ float readlane_f(float v, int lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// Synchronisation inside a factorisation or solve: BlockSync when the
+// workgroup is the one wavefront doing the work; WaveSync when other
+// wavefronts of the workgroup are busy elsewhere (LDS operations of one
+// wavefront are processed in order, so only the compiler must keep the
+// program order).
+struct BlockSync {
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+struct WaveSync {
+    static __device__ __forceinline__ void sync() { __asm__ volatile("" ::: "memory"); }
+};
+
 // BF16 gathers: rows `idx[0..nnz)` of `src` (BF16, row stride `stride`,
 // 16-byte aligned rows) with ratings `vals` (FP32).  Row `sentinel` of `src`
 // is all zeros; positions past nnz gather it, so no load needs a lane mask.
@@ -48,7 +60,7 @@ __device__ __forceinline__ float readlane_f(float v, int lane)
 // ratings, with r' = r - rbar split into two BF16 parts hi = bf16(r') and
 // lo = bf16(r' - hi), so r' is carried to about 2^-17 relative; `rvp` holds
 // CH / 2 packed hi pairs followed by CH / 2 lo pairs.
-template <int KP>
+template <int KP, class Sync = BlockSync>
 __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals, int64_t nnz,
                                           const uint16_t *src, int stride, int32_t sentinel, float rbar,
                                           char *stage, uint32_t *rvp, floatx16 *acc, float &bacc)
@@ -154,15 +166,15 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
             load_rows(c0 + S::CH, j, d, v);
             if (c0 + 2 * S::CH < nnz) load_idx(c0 + 2 * S::CH, j);
         }
-        __syncthreads();
+        Sync::sync();
         multiply_chunk();
-        __syncthreads();
+        Sync::sync();
     }
     if constexpr (KP == 32) bacc += __shfl_xor(bacc, 32);
 }
 
 // FP32 gathers of rows `idx` of `src` (row stride K), Gram on FP32 matrix cores.
-template <int KP>
+template <int KP, class Sync = BlockSync>
 __device__ __forceinline__ void gram_f32(const int32_t *idx, const float *vals, int64_t nnz,
                                          const float *src, int K, float rbar, float *stage,
                                          float *rv, int *sidx, floatx16 *acc, float &bacc)
@@ -176,14 +188,14 @@ __device__ __forceinline__ void gram_f32(const int32_t *idx, const float *vals, 
             sidx[lane] = blend_idx(lane < cnt, idx[c0 + lc], 0);
             rv[lane] = (vals[c0 + lc] - rbar) * (lane < cnt ? 1.0f : 0.0f);
         }
-        __syncthreads();
+        Sync::sync();
 #pragma unroll
         for (int t = 0; t < S::CHF * KP / 64; ++t) {
             const int e = lane + 64 * t;
             const int n = e / KP, f = e % KP;
             stage[n * S::KSF + f] = src[(int64_t)sidx[n] * K + (f < K ? f : K - 1)] * ((n < cnt && f < K) ? 1.0f : 0.0f);
         }
-        __syncthreads();
+        Sync::sync();
 #pragma unroll
         for (int ks = 0; ks < S::CHF / 2; ++ks) {
             const float *sr = stage + (2 * ks + (lane >> 5)) * S::KSF;
@@ -203,7 +215,7 @@ __device__ __forceinline__ void gram_f32(const int32_t *idx, const float *vals, 
             for (int n = 0; n < PER; ++n)
                 bacc = fmaf(stage[(part * PER + n) * S::KSF + f], rv[part * PER + n], bacc);
         }
-        __syncthreads();
+        Sync::sync();
     }
     if constexpr (KP == 32) bacc += __shfl_xor(bacc, 32);
 }
@@ -290,17 +302,6 @@ __device__ __forceinline__ void syrk_trailing(float *A)
         }
 }
 
-// Synchronisation inside a factorisation or solve: BlockSync when the
-// workgroup is the one wavefront doing the work; WaveSync when other
-// wavefronts of the workgroup are busy elsewhere (LDS operations of one
-// wavefront are processed in order, so only the compiler must keep the
-// program order).
-struct BlockSync {
-    static __device__ __forceinline__ void sync() { __syncthreads(); }
-};
-struct WaveSync {
-    static __device__ __forceinline__ void sync() { __asm__ volatile("" ::: "memory"); }
-};
 
 // Factor the KP x KP matrix whose row ri = lane % KP is in A (registers):
 // afterwards A holds row ri of L (lower, L L^T = P) and invbuf[k] = 1/L_kk.
@@ -425,7 +426,7 @@ __device__ __forceinline__ float backward_sub(const float *tri, float invd, floa
 // across the wave) when a pivot is not finite or not above
 // 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with L; `aux` holds 3 KP floats.
 // Lane ri keeps row ri of P in registers through chol_factor.
-template <int KP>
+template <int KP, class Sync = BlockSync>
 __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float bb, float z,
                                             bool &fail)
 {
@@ -440,15 +441,15 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) dg = fmaxf(dg, __shfl_xor(dg, o));
     const float tau = 64.0f * (float)K * 0x1.0p-24f * dg;
-    __syncthreads();
-    chol_factor<KP>(A, invbuf, tri);  // P is in registers: tri serves as the panel buffer
+    Sync::sync();
+    chol_factor<KP, Sync>(A, invbuf, tri);  // P is in registers: tri serves as the panel buffer
     fail = chol_pivots_fail(invbuf[ri], ri, K, tau);
     const float invd = invbuf[ri];
-    const float y = forward_sub<KP>(A, invd, bb, ybuf);
+    const float y = forward_sub<KP, Sync>(A, invd, bb, ybuf);
     store_rows<KP>(A, tri);
-    __syncthreads();
-    const float x = backward_sub<KP>(tri, invd, y + z, xbuf);
-    __syncthreads();
+    Sync::sync();
+    const float x = backward_sub<KP, Sync>(tri, invd, y + z, xbuf);
+    Sync::sync();
     return x;
 }
 

@@ -43,6 +43,14 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(declared_functions()) <= set(_lib.EXPORTS), set(declared_functions()) - set(_lib.EXPORTS)
 
 
+def test_timing_classes_match_the_header():
+    """The binding's timing structure has the header's number of kernel classes."""
+    from paper_1705_10633_amd import _lib
+    n = int(re.search(r"#define BPMF_TIMING_CLASSES (\d+)", open(HEADER).read()).group(1))
+    assert len(_lib.TIMING_CLASSES) == n
+    assert C.sizeof(_lib.Timing) == 16 * n
+
+
 def test_status_strings(lib):
     for code in range(7):
         assert lib.bpmf_status_string(code)

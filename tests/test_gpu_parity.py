@@ -103,11 +103,16 @@ def test_fp64_shapes_and_empty_rows(K, M, N, nnz):
     assert eu.max() <= FP64_TOL and ev.max() <= FP64_TOL
 
 
-def _one_sweep_from_f32_state(prob, precision, tape):
-    """GPU mixed sweep and the FP64 oracle from the same FP32-rounded start."""
+def _f32_start(prob):
     p32 = synth.Problem(**{**prob.__dict__})
     p32.U0 = prob.U0.astype(np.float32).astype(np.float64)
     p32.V0 = prob.V0.astype(np.float32).astype(np.float64)
+    return p32
+
+
+def _one_sweep_from_f32_state(prob, precision, tape):
+    """GPU mixed sweep and the FP64 oracle from the same FP32-rounded start."""
+    p32 = _f32_start(prob)
     ref = O.gibbs(p32, tape, n_sweeps=1, nthreads=8, want_hyper=True)
     s = _run_gpu(p32, tape, 1, precision=precision)
     return s, ref
@@ -137,6 +142,78 @@ def test_mixed_one_sweep_error(precision, K):
           f"V median {np.median(ev):.2e} max {ev.max():.2e}; fallback {s.info()['fallback_rows']}")
     assert np.median(eu) <= med and eu.max() <= mx
     assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx
+
+
+def _few_ratings(K, seed):
+    """Most users keep 0..5 of their ratings, forty keep all of them (~44)."""
+    base = synth.uniform_planted(M=900, N=200, K=K, nnz=40000, seed=seed, n_sweeps=1, burnin=0)
+    R = base.R
+    r = np.repeat(np.arange(R.M), R.row_counts())
+    rng = np.random.default_rng(seed)
+    cap = rng.choice([0, 1, 1, 1, 2, 2, 3, 3, 4, 5], size=R.M)
+    cap[:40] = R.N
+    keep = (np.arange(r.size) - R.row_ptr[r]) < cap[r]
+    p = synth.Problem(**{**base.__dict__})
+    p.R = synth.from_coo(R.M, R.N, r[keep], R.col_idx[keep].astype(np.int64), R.row_val[keep])
+    return p
+
+
+@pytest.mark.parametrize("precision,K", [(p, k) for p in ("fp32", "bf16") for k in (10, 32, 64)])
+def test_rank_one_rows_one_sweep_error(precision, K):
+    """Rows with at most 3 ratings (K <= 32) or 2 (K = 64) are sampled by
+    rank-one updates of chol(Lambda) instead of a Cholesky of P; they meet
+    the same bounds as the rows of the full kernel in the same sweep, and the
+    pivot rule flags none of them."""
+    prob = _few_ratings(K, seed=K + 7)
+    tape = tape_for(prob, 1, seed=K + 3)
+    s, ref = _one_sweep_from_f32_state(prob, precision, tape)
+    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    small = prob.R.row_counts() <= (3 if K <= 32 else 2)
+    assert small.sum() > 400 and (~small).sum() >= 40
+    med, mx = MIXED_TOL[precision]
+    for name, e in (("rank-one", eu[small]), ("full", eu[~small])):
+        print(f"{precision} K={K} {name} users ({e.size}): median {np.median(e):.2e} max {e.max():.2e}")
+        assert np.median(e) <= med and e.max() <= mx
+    print(f"  movies: median {np.median(ev):.2e} max {ev.max():.2e}")
+    assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx
+    assert s.info()["fallback_rows"] == 0
+
+
+def _heavy_rows(K, seed):
+    """Eight users rate 2048..3000 of 3000 movies, the other 292 rate 10..29."""
+    rng = np.random.default_rng(seed)
+    M, N = 300, 3000
+    counts = rng.integers(10, 30, M)
+    counts[:8] = rng.integers(2048, N + 1, 8)
+    rows = np.repeat(np.arange(M), counts)
+    cols = np.concatenate([rng.choice(N, c, replace=False) for c in counts]).astype(np.int64)
+    vals = 3.0 + rng.standard_normal(rows.size)
+    R = synth.from_coo(M, N, rows, cols, vals)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    return synth.Problem("heavy", R, K, 2.0, np.zeros(K), 2.0, float(K), np.eye(K), 1, 0,
+                         f32(0.3 * rng.standard_normal((M, K))), f32(0.3 * rng.standard_normal((N, K))),
+                         np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), 0, float(vals.mean()))
+
+
+@pytest.mark.parametrize("precision,K", [(p, k) for p in ("fp32", "bf16") for k in (20, 64)])
+def test_heavy_rows_one_sweep_error(precision, K):
+    """Rows with at least 2048 ratings split their gathers and Gram over eight
+    wavefronts and sum the partial tiles in a fixed tree; they meet the bounds
+    of the one-wavefront rows, and two runs give identical bits."""
+    prob = _heavy_rows(K, seed=K)
+    tape = tape_for(prob, 1, seed=K + 5)
+    s, ref = _one_sweep_from_f32_state(prob, precision, tape)
+    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    heavy = prob.R.row_counts() >= 2048
+    assert heavy.sum() == 8
+    med, mx = MIXED_TOL[precision]
+    for name, e in (("heavy", eu[heavy]), ("other", eu[~heavy])):
+        print(f"{precision} K={K} {name} users ({e.size}): median {np.median(e):.2e} max {e.max():.2e}")
+        assert np.median(e) <= med and e.max() <= mx
+    again = _run_gpu(_f32_start(prob), tape, 1, precision=precision)
+    import torch
+    assert torch.equal(again.U, s.U) and torch.equal(again.V, s.V)
 
 
 def test_fp32_pivot_failure_falls_back_to_fp64():
