@@ -390,8 +390,13 @@ __device__ __forceinline__ float forward_sub(const float (&A)[KP], float invd, f
     return ybuf[ri];
 }
 
-// Rows of L (lower triangle only: a lane's entries right of its diagonal
-// would land in other rows' slots) into the packed triangle `tri`.
+// Rows of L into the packed triangle `tri` (row r at r(r+1)/2).  Every lane
+// stores its whole row, last column first, one store instruction per column.
+// A lane's entries right of its diagonal (garbage) land in later rows'
+// slots: r(r+1)/2 + c' with r > ri and c' < c, which their owners write at
+// a later step.  The compiler fence keeps the columns in separate
+// instructions: merged into one ds_write2, two lanes could write one slot
+// in the same instruction.
 template <int KP>
 __device__ __forceinline__ void store_rows(const float (&A)[KP], float *tri)
 {
@@ -400,8 +405,10 @@ __device__ __forceinline__ void store_rows(const float (&A)[KP], float *tri)
     const int rbase = ri * (ri + 1) / 2;
     if (lane < KP) {
 #pragma unroll
-        for (int c = 0; c < KP; ++c)
-            if (c <= ri) tri[rbase + c] = A[c];
+        for (int c = KP - 1; c >= 0; --c) {
+            tri[rbase + c] = A[c];
+            __asm__ volatile("" ::: "memory");
+        }
     }
 }
 
