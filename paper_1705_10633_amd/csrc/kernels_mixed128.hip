@@ -197,7 +197,9 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(3, 3))) void
                     const int c = 32 * tb + (lane & 31);
                     const int e = rowoff(r) + c;  // < PTRI2 + K2 for every lane
                     const float val = fmaf(alpha, acc[t][4 * j + i], hyp.Lambda_tri[e]);
-                    if (c <= r) P[e] = val;
+                    // above the diagonal: a slot in the padding after the
+                    // triangle, so the store (and the load) stay unconditional
+                    P[c <= r ? e : PTRI2 + lane] = val;
                 }
         }
     }

@@ -255,18 +255,27 @@ __device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *
 {
     using S = RowShape<KP>;
     const int lane = threadIdx.x & 63;
+    const unsigned hh = (unsigned)lane >> 5, cc = (unsigned)lane & 31u;
+    const unsigned pad = KP * (KP + 1) / 2 + (unsigned)(lane % KP);
 #pragma unroll
     for (int t = 0; t < S::NTILE; ++t) {
         const int ta = (t == 0) ? 0 : 1, tb = (t == 2) ? 1 : 0;
+        const unsigned c = 32u * tb + cc;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int r = 32 * ta + 8 * j + 4 * (lane >> 5) + i;
-                const int c = 32 * tb + (lane & 31);
-                const int e = r * (r + 1) / 2 + c;  // < KP (KP + 3) / 2 for every lane
+                // entry (r, c), r = R + 4 hh with R = 32 ta + 8 j + i:
+                // r (r + 1) / 2 = R (R + 1) / 2 + hh (4 R + 10)
+                const unsigned R = 32u * ta + 8u * j + i;
+                const unsigned r = R + 4u * hh;
+                const unsigned e = R * (R + 1) / 2 + hh * (4u * R + 10u) + c;  // < KP (KP + 3) / 2
                 const float v = fmaf(alpha, acc[t][4 * j + i], lamtri[e]);
-                if (c <= r) tri[e] = v;
+                // entries above the diagonal go to the lane's own slot in the
+                // padding after the triangle: the store stays unconditional,
+                // so the compiler cannot sink the load of Lambda behind a
+                // branch of its own (one wait per entry)
+                tri[(t == 1 || c <= r) ? e : pad] = v;
             }
     }
 }
