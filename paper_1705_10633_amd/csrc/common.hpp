@@ -80,12 +80,11 @@ __device__ __forceinline__ int blend_idx(bool ok, int v, int other)
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) {  // inf or nan
-        return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    }
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    // one v_cvt_pk_bf16_f32 on gfx950: round to nearest even, NaN stays NaN
+    const __bf16 h = (__bf16)f;
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h)

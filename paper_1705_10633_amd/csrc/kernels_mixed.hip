@@ -56,8 +56,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     float *tri = u;
     store_precision_tri<KP>(tri, acc, alpha, hyp.Lambda_tri);
     const int ri = lane % KP;
-    const float lmu = hyp.Lmu_f[ri < K ? ri : 0];
-    const float bb = (ri < K) ? fmaf(alpha, bacc, lmu) : 0.0f;
+    // unconditional load and a multiplicative mask: as a select, the load
+    // would be moved behind a branch with its own wait
+    const float bb = fmaf(alpha, bacc, hyp.Lmu_f[ri < K ? ri : 0]) * (ri < K ? 1.0f : 0.0f);
 
     float z;
     if (draws.tape_rows) {
@@ -167,8 +168,7 @@ __global__ __launch_bounds__(64 * HW) void rows_heavy_kernel(SideArgs a, int K, 
     float *tri = u[0];
     store_precision_tri<KP>(tri, acc, alpha, hyp.Lambda_tri);
     const int ri = lane % KP;
-    const float lmu = hyp.Lmu_f[ri < K ? ri : 0];
-    const float bb = (ri < K) ? fmaf(alpha, bacc, lmu) : 0.0f;
+    const float bb = fmaf(alpha, bacc, hyp.Lmu_f[ri < K ? ri : 0]) * (ri < K ? 1.0f : 0.0f);
     float z;
     if (draws.tape_rows) {
         z = (ri < K) ? (float)draws.tape_rows[(int64_t)row * K + ri] : 0.0f;

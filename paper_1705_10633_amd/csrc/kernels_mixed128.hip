@@ -204,8 +204,7 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         }
     }
     if (tid < K2) {
-        const float lmu = hyp.Lmu_f[tid < K ? tid : 0];
-        bvec[tid] = tid < K ? fmaf(alpha, bacc, lmu) : 0.0f;
+        bvec[tid] = fmaf(alpha, bacc, hyp.Lmu_f[tid < K ? tid : 0]) * (tid < K ? 1.0f : 0.0f);
     }
     if (draws.tape_rows) {
         if (tid < K2) zvec[tid] = tid < K ? (float)draws.tape_rows[(int64_t)row * K + (tid < K ? tid : 0)] : 0.0f;
