@@ -66,7 +66,7 @@ struct WsLayout {
 
 struct Offsets {
     size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], lchol[2], nwd[2], mu0, w0inv,
-        order[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
+        order[2], rowtab[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
 
@@ -112,6 +112,7 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
         o.lchol[s] = w.add((mk && K <= 64) ? sizeof(float) * (size_t)padded_k(K) * (padded_k(K) + 4) : 0);
         o.nwd[s] = w.add(sizeof(double) * (size_t)(2 * K + K * (K - 1) / 2));
         o.order[s] = w.add(sizeof(int32_t) * n[s]);
+        o.rowtab[s] = w.add(sizeof(int4) * n[s]);
         o.fblist[s] = w.add(mk ? sizeof(int32_t) * n[s] : 0);
         // BF16 copy plus one all-zero row (the gather target past a row's end)
         o.shadow[s] = w.add((mk && p->precision == BPMF_BF16) ? sizeof(uint16_t) * (n[s] + 1) * padded_k(K) : 0);
@@ -404,6 +405,17 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
             return pp[a + 1] - pp[a] > pp[b + 1] - pp[b];
         });
         HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.order[sd]), ord.data(), sizeof(int32_t) * n[sd], hipMemcpyHostToDevice, s));
+        {
+            std::vector<int4> tab(n[sd]);
+            for (int64_t q = 0; q < n[sd]; ++q) {
+                const int64_t b = pp[ord[q]];
+                tab[q] = make_int4(ord[q], (int)(pp[ord[q] + 1] - b), (int)(uint32_t)(uint64_t)b,
+                                   (int)(uint32_t)((uint64_t)b >> 32));
+            }
+            HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.rowtab[sd]), tab.data(), sizeof(int4) * n[sd],
+                                    hipMemcpyHostToDevice, s));
+            HIP_OK_C(hipStreamSynchronize(s));
+        }
         HIP_OK_C(hipStreamSynchronize(s));
         if (c->hyp[sd].Lchol) {
             const int64_t lim = rank1_limit(K);
@@ -582,6 +594,7 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
     a.X = side == 0 ? c->dU : c->dV;
     a.other = side == 0 ? c->dV : c->dU;
     a.order = c->at<int32_t>(c->off.order[side]);
+    a.rowtab = c->at<int4>(c->off.rowtab[side]);
     a.shadow_stride = c->KP;
     hipEvent_t t0;
     if (f64) {
@@ -620,6 +633,7 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
         }
         SideArgs ab = a;
         ab.order = a.order + nh;
+        ab.rowtab = a.rowtab + nh;
         ab.n_rows = n - ns - nh;
         t0 = time_begin(c, s);
         HIP_OK(launch_rows_mixed(ab, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, s));

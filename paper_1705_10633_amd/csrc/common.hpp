@@ -67,6 +67,9 @@ struct SideArgs {
     uint16_t *X_bf16;       // BF16 copy of this side (output), or NULL
     int32_t shadow_stride;  // row stride of the BF16 copies
     const int32_t *order;   // rows in processing order (nnz descending)
+    // per order slot {row, rating count, first rating (low, high word)}: one
+    // 16-byte load instead of the order entry and then the row pointers
+    const int4 *rowtab;
 };
 
 // Masked loads are written as an unconditional load (from a clamped, valid

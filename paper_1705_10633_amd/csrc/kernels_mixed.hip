@@ -34,9 +34,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     __shared__ int sidx[16];
 
     const int lane = threadIdx.x;
-    const int64_t slot = blockIdx.x;
-    const int row = a.order ? a.order[slot] : (int)slot;
-    const int64_t s0 = a.ptr[row], s1 = a.ptr[row + 1];
+    const int4 rt = a.rowtab[blockIdx.x];
+    const int row = rt.x;
+    const int64_t s0 = (int64_t)(((uint64_t)(uint32_t)rt.w << 32) | (uint32_t)rt.z), s1 = s0 + rt.y;
     const float *vals = (const float *)a.val;
 
     floatx16 acc[S::NTILE];

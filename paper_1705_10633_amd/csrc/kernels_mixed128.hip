@@ -68,9 +68,9 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     __shared__ int fails[2];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t slot = blockIdx.x;
-    const int row = sa.order ? sa.order[slot] : (int)slot;
-    const int64_t s0 = sa.ptr[row], s1 = sa.ptr[row + 1];
+    const int4 rt = sa.rowtab[blockIdx.x];
+    const int row = rt.x;
+    const int64_t s0 = (int64_t)(((uint64_t)(uint32_t)rt.w << 32) | (uint32_t)rt.z), s1 = s0 + rt.y;
     const int64_t nnz = s1 - s0;
     const int32_t *idx = sa.idx + s0;
     const float *vals = (const float *)sa.val + s0;
