@@ -40,7 +40,9 @@ constexpr int SB2 = CH2 * 2 + 16;             // bytes per staged feature row
 constexpr int PTRI2 = K2 * (K2 + 1) / 2;      // packed lower triangle of P
 constexpr int STAGE2 = K2 * SB2 / 4;          // staging (floats)
 constexpr int U2 = (PTRI2 + K2) > STAGE2 ? (PTRI2 + K2) : STAGE2;
-constexpr int LTRI2 = H2 * (H2 + 1) / 2 + H2; // packed 64 x 64 triangle + pad
+// L22 is stored in place of P22: row q of the block starts at
+// rowoff(H2 + q) + H2 = P22OFF + q (q + 1) / 2 + H2 q
+constexpr int P22OFF = H2 * (H2 + 1) / 2 + H2;
 
 __device__ __forceinline__ int rowoff(int r) { return r * (r + 1) / 2; }
 
@@ -53,13 +55,13 @@ __device__ __forceinline__ void tile_of(int wave, int t, int &a, int &b)
     b = wave == 0 ? (t == 2 ? 1 : 0) : (wave == 3 ? 2 + t : t);
 }
 
-__global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(3, 3))) void rows_mixed128_kernel(
+__global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void rows_mixed128_kernel(
     SideArgs sa, int K, float alpha, float rbar, HyperDev hyp, DrawSrc draws, int32_t *fb_list,
     DevState *state, int side)
 {
     __shared__ __attribute__((aligned(16))) float u[U2];     // staging, then P (packed), then L11 / L21 in place
-    __shared__ __attribute__((aligned(16))) float l22[LTRI2]; // L22 (packed)
-    __shared__ __attribute__((aligned(16))) float pb0[H2 * 12], pb2[H2 * 12];
+    // panel buffer of the two 64-wide factorisations (never at the same time)
+    __shared__ __attribute__((aligned(16))) float pb[H2 * 12];
     __shared__ __attribute__((aligned(16))) float bvec[K2], zvec[K2];
     __shared__ __attribute__((aligned(16))) float y1[H2], b2[H2], x2v[H2], inv11[H2], inv22[H2], yb2[H2],
         xb2[H2], xb0[H2];
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 #pragma unroll
         for (int c = 0; c < H2; ++c) A[c] = P[rowoff(lane) + c];
         WaveSync::sync();
-        chol_factor<H2, WaveSync>(A, inv11, pb0);
+        chol_factor<H2, WaveSync>(A, inv11, pb);
         const float iv = inv11[lane];
         const bool f0 = chol_pivots_fail(iv, lane, K < H2 ? K : H2, tau);
         if (lane == 0) fails[0] = f0 ? 1 : 0;
@@ -307,14 +309,15 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 #pragma unroll
         for (int c = 0; c < H2; ++c) A[c] = P[rowoff(H2 + lane) + H2 + c];
         WaveSync::sync();
-        chol_factor<H2, WaveSync>(A, inv22, pb2);
+        chol_factor<H2, WaveSync>(A, inv22, pb);
         const float iv = inv22[lane];
         const bool f2 = chol_pivots_fail(iv, lane, K - H2, tau);
         if (lane == 0) fails[1] = f2 ? 1 : 0;
         const float y = forward_sub<H2, WaveSync>(A, iv, b2[lane], yb2);
-        store_rows<H2>(A, l22);
+        // masked: past its diagonal a row would run into the next row's L21
+        store_rows_lower<H2, H2>(A, P + P22OFF);
         WaveSync::sync();
-        x2v[lane] = backward_sub<H2, WaveSync>(l22, iv, y + zvec[H2 + lane], xb2);
+        x2v[lane] = backward_sub<H2, WaveSync, H2>(P + P22OFF, iv, y + zvec[H2 + lane], xb2);
     }
     __syncthreads();
 

@@ -421,9 +421,27 @@ __device__ __forceinline__ void store_rows(const float (&A)[KP], float *tri)
     }
 }
 
-// x = L^{-T} w with L packed in `tri` and w_ri in w; returns x_ri.  xbuf
-// holds KP floats.
-template <int KP, class Sync = BlockSync>
+// Lower triangle of the rows of L only (lane-masked), into a packed layout
+// whose row r starts at r(r+1)/2 + G r: G = 0 is the plain packed triangle,
+// G > 0 a triangle embedded in a larger packed one (row r of the block at
+// column offset G of row G + r), where the entries right of the diagonal
+// would overwrite other data.
+template <int KP, int G>
+__device__ __forceinline__ void store_rows_lower(const float (&A)[KP], float *tri)
+{
+    const int lane = threadIdx.x & 63;
+    const int ri = lane % KP;
+    const int rbase = ri * (ri + 1) / 2 + G * ri;
+    if (lane < KP) {
+#pragma unroll
+        for (int c = 0; c < KP; ++c)
+            if (c <= ri) tri[rbase + c] = A[c];
+    }
+}
+
+// x = L^{-T} w with L packed in `tri` (row r at r(r+1)/2 + G r) and w_ri in
+// w; returns x_ri.  xbuf holds KP floats.
+template <int KP, class Sync = BlockSync, int G = 0>
 __device__ __forceinline__ float backward_sub(const float *tri, float invd, float w, float *xbuf)
 {
     const int ri = (threadIdx.x & 63) % KP;
@@ -431,7 +449,7 @@ __device__ __forceinline__ float backward_sub(const float *tri, float invd, floa
     for (int k = KP - 1; k >= 0; --k) {
         const float xk = readlane_f(w * invd, k);
         xbuf[k] = xk;
-        w = fmaf(-tri[k * (k + 1) / 2 + ri], xk, w);
+        w = fmaf(-tri[k * (k + 1) / 2 + G * k + ri], xk, w);
     }
     Sync::sync();
     return xbuf[ri];
