@@ -188,8 +188,9 @@ bpmf_status bpmf_state_restore(bpmf_ctx *ctx, const void *h_buf, size_t bytes, v
  * [0] side statistics, [1] hyper-parameter step, [2] users' row update,
  * [3] movies' row update, [4] FP64 recompute of flagged rows,
  * [5] predictions, [6] sweep counter, [7] rank-one row update of rows with
- * very few ratings, [8] multi-wavefront row update of rows with very many
- * ratings (both sides; [7] and [8] FP32/BF16 with K <= 64). */
+ * very few ratings, [8] factorisation of rows with very many ratings, whose
+ * Gram was computed in pieces within [2] / [3] (both sides; [7] and [8]
+ * FP32/BF16 with K <= 64). */
 #define BPMF_TIMING_CLASSES 9
 typedef struct {
     double ms[BPMF_TIMING_CLASSES];

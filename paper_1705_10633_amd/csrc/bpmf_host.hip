@@ -66,11 +66,15 @@ struct WsLayout {
 
 struct Offsets {
     size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], lchol[2], nwd[2], mu0, w0inv,
-        order[2], rowtab[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
+        order[2], rowtab[2], ctab[2], part[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
 
 static int padded_k(int K) { return K <= 32 ? 32 : (K <= 64 ? 64 : 128); }
+
+// Pieces of heavy rows per side (workspace reserved up front): rows with at
+// least heavy_min_ratings() ratings are cut into pieces of at least 512.
+static constexpr int64_t kMaxPieces = 2048;
 
 // Mixed-precision row kernels: one wavefront per row for K <= 64 (FP32 or
 // BF16 gathers); a four-wavefront workgroup per row for 64 < K <= 128 (BF16
@@ -112,7 +116,11 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
         o.lchol[s] = w.add((mk && K <= 64) ? sizeof(float) * (size_t)padded_k(K) * (padded_k(K) + 4) : 0);
         o.nwd[s] = w.add(sizeof(double) * (size_t)(2 * K + K * (K - 1) / 2));
         o.order[s] = w.add(sizeof(int32_t) * n[s]);
-        o.rowtab[s] = w.add(sizeof(int4) * n[s]);
+        // launch table: the rows, or (with heavy rows) their pieces and then the other rows
+        const bool pieces = mk && K <= 64;
+        o.rowtab[s] = w.add(sizeof(int4) * (n[s] + (pieces ? kMaxPieces : 0)));
+        o.ctab[s] = w.add(pieces ? sizeof(int4) * kMaxPieces / 2 : 0);
+        o.part[s] = w.add(pieces ? sizeof(float) * (size_t)kMaxPieces * piece_floats(padded_k(K)) : 0);
         o.fblist[s] = w.add(mk ? sizeof(int32_t) * n[s] : 0);
         // BF16 copy plus one all-zero row (the gather target past a row's end)
         o.shadow[s] = w.add((mk && p->precision == BPMF_BF16) ? sizeof(uint16_t) * (n[s] + 1) * padded_k(K) : 0);
@@ -143,8 +151,9 @@ struct bpmf_ctx {
     // tails of the row order: rows for the rank-one kernels (n_small), of
     // which the last n_tiny (at most one rating, K <= 32) take the one-lane kernel
     int64_t n_small[2] = {0, 0}, n_tiny[2] = {0, 0};
-    // head of the row order: rows for the multi-wavefront kernel (K <= 64)
-    int64_t n_heavy[2] = {0, 0};
+    // head of the row order: heavy rows cut into pieces (K <= 64); the launch
+    // table holds n_pieces pieces and then the rows from slot n_heavy on
+    int64_t n_heavy[2] = {0, 0}, n_pieces[2] = {0, 0};
     int64_t n_test;
     const int32_t *test_rows, *test_cols;
     hipGraph_t graph = nullptr;
@@ -405,22 +414,15 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
             return pp[a + 1] - pp[a] > pp[b + 1] - pp[b];
         });
         HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.order[sd]), ord.data(), sizeof(int32_t) * n[sd], hipMemcpyHostToDevice, s));
-        {
-            std::vector<int4> tab(n[sd]);
-            for (int64_t q = 0; q < n[sd]; ++q) {
-                const int64_t b = pp[ord[q]];
-                tab[q] = make_int4(ord[q], (int)(pp[ord[q] + 1] - b), (int)(uint32_t)(uint64_t)b,
-                                   (int)(uint32_t)((uint64_t)b >> 32));
-            }
-            HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.rowtab[sd]), tab.data(), sizeof(int4) * n[sd],
-                                    hipMemcpyHostToDevice, s));
-            HIP_OK_C(hipStreamSynchronize(s));
-        }
-        HIP_OK_C(hipStreamSynchronize(s));
+        auto entry = [&](int64_t q) {
+            const int64_t b = pp[ord[q]];
+            return make_int4(ord[q], (int)(pp[ord[q] + 1] - b), (int)(uint32_t)(uint64_t)b,
+                             (int)(uint32_t)((uint64_t)b >> 32));
+        };
+        int64_t nh = 0, ns = 0, nt = 0;
         if (c->hyp[sd].Lchol) {
             const int64_t lim = rank1_limit(K);
-            int64_t m = 0;
-            int64_t t = 0;
+            int64_t m = 0, t = 0;
             while (m < n[sd] && pp[ord[n[sd] - 1 - m] + 1] - pp[ord[n[sd] - 1 - m]] <= lim) {
                 if (pp[ord[n[sd] - 1 - m] + 1] - pp[ord[n[sd] - 1 - m]] <= 1) ++t;
                 ++m;
@@ -428,19 +430,47 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
             // a short tail finishes inside the full kernel's launch anyway;
             // a separate launch pays off once it is a sizeable share of the rows
             if (m >= 16384 || 16 * m >= n[sd]) {
-                c->n_small[sd] = m;
-                c->n_tiny[sd] = K <= 32 ? t : 0;
+                ns = m;
+                nt = K <= 32 ? t : 0;
             }
-            // the multi-wavefront launch runs before the one-wavefront launch;
-            // it pays off when the heavy rows hold a sizeable share of the
-            // ratings (otherwise they finish inside the one-wavefront launch)
+            // heavy rows: worth the extra combine launch when they hold a
+            // sizeable share of the ratings (otherwise they finish inside
+            // the one-wavefront launch anyway)
             int64_t hv = 0, hnnz = 0;
-            while (hv < n[sd] - m && pp[ord[hv] + 1] - pp[ord[hv]] >= heavy_min_ratings()) {
+            while (hv < n[sd] - m && hv < kMaxPieces / 2 && pp[ord[hv] + 1] - pp[ord[hv]] >= heavy_min_ratings()) {
                 hnnz += pp[ord[hv] + 1] - pp[ord[hv]];
                 ++hv;
             }
-            c->n_heavy[sd] = 10 * hnnz >= R->nnz ? hv : 0;
+            if (10 * hnnz >= R->nnz) nh = hv;
+            c->n_small[sd] = ns;
+            c->n_tiny[sd] = nt;
         }
+        std::vector<int4> tab, ctab;
+        if (nh > 0) {
+            int64_t hnnz = 0;
+            for (int64_t q = 0; q < nh; ++q) hnnz += pp[ord[q] + 1] - pp[ord[q]];
+            // sum over rows of ceil(nnz / psz) <= hnnz / psz + nh <= kMaxPieces
+            const int64_t psz = std::max<int64_t>(512, (hnnz + kMaxPieces - nh - 1) / (kMaxPieces - nh));
+            for (int64_t q = 0; q < nh; ++q) {
+                const int64_t b = pp[ord[q]], e = pp[ord[q] + 1];
+                ctab.push_back(make_int4(ord[q], (int)tab.size(), 0, 0));
+                for (int64_t x = b; x < e; x += psz) {
+                    const int64_t cnt = std::min<int64_t>(psz, e - x);
+                    tab.push_back(make_int4(-(int)tab.size() - 1, (int)cnt, (int)(uint32_t)(uint64_t)x,
+                                            (int)(uint32_t)((uint64_t)x >> 32)));
+                }
+                ctab.back().z = (int)tab.size() - ctab.back().y;
+            }
+        }
+        c->n_heavy[sd] = nh;
+        c->n_pieces[sd] = (int64_t)tab.size();
+        for (int64_t q = nh; q < n[sd]; ++q) tab.push_back(entry(q));
+        HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.rowtab[sd]), tab.data(), sizeof(int4) * tab.size(),
+                                hipMemcpyHostToDevice, s));
+        if (!ctab.empty())
+            HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.ctab[sd]), ctab.data(), sizeof(int4) * ctab.size(),
+                                    hipMemcpyHostToDevice, s));
+        HIP_OK_C(hipStreamSynchronize(s));
     }
     // held-out pairs sorted by user (then movie) so that predictions reuse rows
     if (n_test > 0) {
@@ -621,23 +651,25 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
     }
     int32_t *fbl = c->at<int32_t>(c->off.fblist[side]);
     if (K <= 64) {
-        // order slots: [0, nh) heavy rows, [nh, n - ns) one wavefront per row,
-        // [n - ns, n - nt) rank-one updates, [n - nt, n) one lane per row
-        const int64_t nh = c->n_heavy[side], ns = c->n_small[side], nt = c->n_tiny[side];
+        // order slots: [0, nh) heavy rows (as np pieces, then one combine
+        // entry each), [nh, n - ns) one wavefront per row, [n - ns, n - nt)
+        // rank-one updates, [n - nt, n) one lane per row
+        const int64_t nh = c->n_heavy[side], np = c->n_pieces[side], ns = c->n_small[side], nt = c->n_tiny[side];
+        PieceArgs pc;
+        pc.part = c->at<float>(c->off.part[side]);
+        pc.ctab = c->at<int4>(c->off.ctab[side]);
+        pc.combine = 0;
+        t0 = time_begin(c, s);
+        HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, pc,
+                                 np + (n - ns - nh), s));
+        time_end(c, 2 + side, t0, s);
         if (nh > 0) {
-            SideArgs ah = a;
-            ah.n_rows = nh;
+            pc.combine = 1;
             t0 = time_begin(c, s);
-            HIP_OK(launch_rows_heavy(ah, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, s));
+            HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state,
+                                     pc, nh, s));
             time_end(c, 8, t0, s);
         }
-        SideArgs ab = a;
-        ab.order = a.order + nh;
-        ab.rowtab = a.rowtab + nh;
-        ab.n_rows = n - ns - nh;
-        t0 = time_begin(c, s);
-        HIP_OK(launch_rows_mixed(ab, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, s));
-        time_end(c, 2 + side, t0, s);
         if (ns > 0) {
             t0 = time_begin(c, s);
             HIP_OK(launch_rows_rank1(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state,

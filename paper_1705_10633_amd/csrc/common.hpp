@@ -131,14 +131,21 @@ hipError_t launch_rows_f64(const SideArgs &a, int K, double alpha, double rbar,
                            DevState *state, hipStream_t s);
 hipError_t launch_rows_mixed128(const SideArgs &a, int K, double alpha, double rbar, HyperDev hyp,
                                 DrawSrc draws, int32_t *fb_list, DevState *state, hipStream_t s);
+// Pieces of heavy rows (see rows_mixed_kernel): per piece, the partial Gram
+// tiles in accumulator layout plus the right-hand side, floats per piece:
+__host__ __device__ constexpr int piece_floats(int KP) { return (KP == 64 ? 3 : 1) * 16 * 64 + 64; }
+struct PieceArgs {
+    float *part;        // piece partial sums
+    const int4 *ctab;   // combine launch: per heavy row {row, first piece, piece count, 0}
+    int32_t combine;    // 0: the launch table a.rowtab (pieces then rows); 1: combine
+};
+// n_entries entries of a.rowtab (pieces have row < 0), or with pc.combine
+// n_entries heavy rows from pc.ctab.
 hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double alpha,
                              double rbar, HyperDev hyp, DrawSrc draws, int32_t *fb_list,
-                             DevState *state, hipStream_t s);
-// The first a.n_rows rows of a.order, each with at least heavy_min_ratings()
-// ratings: gathers and Gram split over several wavefronts per row (K <= 64).
+                             DevState *state, PieceArgs pc, int64_t n_entries, hipStream_t s);
+// Rows with at least this many ratings are cut into pieces (K <= 64).
 int heavy_min_ratings();
-hipError_t launch_rows_heavy(const SideArgs &a, int K, int KP, int bf16, double alpha, double rbar, HyperDev hyp,
-                             DrawSrc draws, int32_t *fb_list, DevState *state, hipStream_t s);
 // Rows in order slots [slot0, slot1), each with at most rank1_max_ratings()
 // ratings, by rank-one updates of chol(Lambda) (K <= 64, hyp.Lchol set).
 int rank1_max_ratings();
