@@ -65,7 +65,7 @@ struct WsLayout {
 };
 
 struct Offsets {
-    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], lchol[2], nwd[2], mu0, w0inv,
+    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], lamacc[2], lchol[2], nwd[2], mu0, w0inv,
         order[2], rowtab[2], ctab[2], part[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
@@ -113,6 +113,7 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
         o.lamf[s] = w.add(sizeof(float) * K * K);
         o.lmuf[s] = w.add(sizeof(float) * K);
         o.lamt[s] = w.add(sizeof(float) * (size_t)padded_k(K) * (padded_k(K) + 3) / 2);
+        o.lamacc[s] = w.add((mk && K <= 64) ? sizeof(float) * 3 * 16 * 64 : 0);
         o.lchol[s] = w.add((mk && K <= 64) ? sizeof(float) * (size_t)padded_k(K) * (padded_k(K) + 4) : 0);
         o.nwd[s] = w.add(sizeof(double) * (size_t)(2 * K + K * (K - 1) / 2));
         o.order[s] = w.add(sizeof(int32_t) * n[s]);
@@ -373,6 +374,8 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         c->hyp[sd].Lambda_f = c->at<float>(off.lamf[sd]);
         c->hyp[sd].Lmu_f = c->at<float>(off.lmuf[sd]);
         c->hyp[sd].Lambda_tri = c->at<float>(off.lamt[sd]);
+        c->hyp[sd].Lambda_acc = (mixed_supported(K, p->precision) && p->precision != BPMF_FP64 && K <= 64)
+                                    ? c->at<float>(off.lamacc[sd]) : nullptr;
         c->hyp[sd].Lchol = (mixed_supported(K, p->precision) && p->precision != BPMF_FP64 && K <= 64)
                                ? c->at<float>(off.lchol[sd]) : nullptr;
     }

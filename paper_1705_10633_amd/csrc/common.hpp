@@ -46,6 +46,11 @@ struct HyperDev {
     // FP32 Lambda as the mixed row kernel's packed lower triangle of the
     // padded size KP (row r at r (r + 1) / 2, identity in the padding), KP (KP + 3) / 2 floats
     float *Lambda_tri;
+    // FP32 Lambda in the K <= 64 row kernel's Gram accumulator layout, or
+    // NULL: entry (t * 16 + e) * 64 + l is Lambda[r][c] of lower 32 x 32
+    // tile t ((0,0), (1,0), (1,1)), r = 32 a + 8 (e / 4) + 4 (l / 32) + e % 4,
+    // c = 32 b + l % 32 (identity in the padding)
+    float *Lambda_acc;
     // chol(Lambda) in FP32 for the rank-one row paths (K <= 64), or NULL:
     // KP x KP row-major (lower; identity in the padding), then KP floats each
     // of 1 / L_ii, L^T mu (= L^{-1} Lambda mu), Lambda_ii (0 in the padding)
@@ -134,6 +139,17 @@ hipError_t launch_rows_mixed128(const SideArgs &a, int K, double alpha, double r
 // Pieces of heavy rows (see rows_mixed_kernel): per piece, the partial Gram
 // tiles in accumulator layout plus the right-hand side, floats per piece:
 __host__ __device__ constexpr int piece_floats(int KP) { return (KP == 64 ? 3 : 1) * 16 * 64 + 64; }
+
+// Position of Lambda[r][c] (r >= c, both < 64) in the accumulator layout of
+// HyperDev::Lambda_acc (-1 for an upper tile).
+__host__ __device__ inline int lambda_acc_index(int r, int c)
+{
+    const int ta = r >> 5, tb = c >> 5;
+    if (ta < tb) return -1;
+    const int t = ta == 0 ? 0 : (tb == 0 ? 1 : 2);
+    const int rr = r & 31;
+    return (t * 16 + 4 * (rr >> 3) + (rr & 3)) * 64 + 32 * ((rr >> 2) & 1) + (c & 31);
+}
 struct PieceArgs {
     float *part;        // piece partial sums
     const int4 *ctab;   // combine launch: per heavy row {row, first piece, piece count, 0}

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
 
     float *tri = u;
-    store_precision_tri<KP>(tri, acc, alpha, hyp.Lambda_tri);
+    store_precision_tri<KP>(tri, acc, alpha, hyp.Lambda_acc);
     const int ri = lane % KP;
     // unconditional load and a multiplicative mask: as a select, the load
     // would be moved behind a branch with its own wait

@@ -444,6 +444,10 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
             }
             if (c <= a && a < KPm)
                 hyp.Lambda_tri[a * (a + 1) / 2 + c] = (a < K && c < K) ? (float)acc[cc] : (a == c ? 1.0f : 0.0f);
+            if (hyp.Lambda_acc && a < KPm && c < KPm) {
+                const int q = lambda_acc_index(a, c);
+                if (q >= 0) hyp.Lambda_acc[q] = (a < K && c < K) ? (float)acc[cc] : (a == c ? 1.0f : 0.0f);
+            }
             // T is chol(Lambda): lower with a positive diagonal, Lambda = T T^T
             if (hyp.Lchol && a < KPm && c < KPm)
                 hyp.Lchol[a * KPm + c] =
@@ -477,13 +481,18 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
 }
 
-// Lambda_tri from Lambda_f (after a state restore).
+// Lambda_tri (and Lambda_acc) from Lambda_f (after a state restore, and
+// after the Normal-Wishart step for K > 64).
 __global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, int KP)
 {
     for (int t = threadIdx.x; t < KP * KP; t += blockDim.x) {
         const int r = t / KP, c = t - r * KP;
-        if (c <= r)
-            hyp.Lambda_tri[r * (r + 1) / 2 + c] = (r < K && c < K) ? hyp.Lambda_f[r * K + c] : (r == c ? 1.0f : 0.0f);
+        const float v = (r < K && c < K) ? hyp.Lambda_f[r * K + c] : (r == c ? 1.0f : 0.0f);
+        if (c <= r) hyp.Lambda_tri[r * (r + 1) / 2 + c] = v;
+        if (hyp.Lambda_acc && KP <= 64) {
+            const int q = lambda_acc_index(r, c);
+            if (q >= 0) hyp.Lambda_acc[q] = v;
+        }
     }
 }
 

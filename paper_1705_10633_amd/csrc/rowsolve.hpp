@@ -249,33 +249,41 @@ __device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc,
 // The same from Lambda stored as the padded packed triangle `lamtri` (the
 // padding entries of the Gram are zero): no index checks, and every load and
 // store uses the same offset.
+// P = Lambda + alpha G into the packed triangle `tri`, from the Gram
+// accumulators and Lambda in the same accumulator layout (`lamacc`, so each
+// load is one coalesced 256-byte access at a fixed offset).
 template <int KP>
 __device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *acc, float alpha,
-                                                    const float *lamtri)
+                                                    const float *lamacc)
 {
     using S = RowShape<KP>;
     const int lane = threadIdx.x & 63;
-    const unsigned hh = (unsigned)lane >> 5, cc = (unsigned)lane & 31u;
-    const unsigned pad = KP * (KP + 1) / 2 + (unsigned)(lane % KP);
+    const int hh = lane >> 5, cc = lane & 31;
+    // Entry (r, c) of tile (ta, tb), r = R + 4 hh with R = 32 ta + 8 j + i,
+    // c = 32 tb + cc, sits at r (r + 1) / 2 + c = R (R + 1) / 2 + 4 hh R +
+    // (10 hh + c).  In bytes: a per-lane part R * 16 hh + 4 (10 hh + c) and
+    // a compile-time part 4 R (R + 1) / 2 that goes into the store's offset.
+    const unsigned u16 = 16u * hh, v4 = 4u * (10u * hh + cc);
+    // entries above the diagonal of a diagonal tile (cc - 4 hh > 8 j + i) go
+    // to the lane's own slot in the padding after the triangle: the store
+    // stays unconditional, so the compiler cannot sink the load of Lambda
+    // behind a branch of its own
+    const unsigned pad4 = 4u * (KP * (KP + 1) / 2 + (unsigned)(lane % KP));
+    const int above = cc - 4 * hh;
+    char *base = (char *)tri;
 #pragma unroll
     for (int t = 0; t < S::NTILE; ++t) {
         const int ta = (t == 0) ? 0 : 1, tb = (t == 2) ? 1 : 0;
-        const unsigned c = 32u * tb + cc;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                // entry (r, c), r = R + 4 hh with R = 32 ta + 8 j + i:
-                // r (r + 1) / 2 = R (R + 1) / 2 + hh (4 R + 10)
                 const unsigned R = 32u * ta + 8u * j + i;
-                const unsigned r = R + 4u * hh;
-                const unsigned e = R * (R + 1) / 2 + hh * (4u * R + 10u) + c;  // < KP (KP + 3) / 2
-                const float v = fmaf(alpha, acc[t][4 * j + i], lamtri[e]);
-                // entries above the diagonal go to the lane's own slot in the
-                // padding after the triangle: the store stays unconditional,
-                // so the compiler cannot sink the load of Lambda behind a
-                // branch of its own (one wait per entry)
-                tri[(t == 1 || c <= r) ? e : pad] = v;
+                const unsigned fixed = 4u * (R * (R + 1) / 2);
+                const float v = fmaf(alpha, acc[t][4 * j + i], lamacc[(t * 16 + 4 * j + i) * 64 + lane]);
+                unsigned off = R * u16 + v4 + 128u * tb;
+                if (t != 1) off = above > 8 * j + i ? pad4 - fixed : off;
+                *(float *)(base + off + fixed) = v;
             }
     }
 }
