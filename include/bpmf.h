@@ -271,9 +271,27 @@ bpmf_status bpmf_server_create(bpmf_server **srv, const bpmf_foldin_model *m,
                                size_t mem_budget_bytes, int32_t n_streams, int32_t max_batch,
                                int32_t max_inflight);
 
+/* Resident mode: no launch and no host-issued copy per request.  One
+ * persistent kernel owns n_slots request slots (at most max_nnz ratings and
+ * max_q queries each) in coherent pinned
+ * host memory; the dispatcher writes a queued request into a free slot, the
+ * kernel computes it (one workgroup per slot, one wavefront in it per stored
+ * sample, the same arithmetic as bpmf_foldin, so the same predictions) and
+ * writes the predictions back.  A request's samples share one compute unit,
+ * so large requests take longer than in batching mode, which spreads them.
+ * The kernel ends after idle_polls polls without a request (0: 500000, about
+ * a second) or when the server is destroyed, and is launched again when a
+ * request waits.  submit / poll / drain / replay / stats / destroy work as in
+ * batching mode; stats count each request as a batch of one.
+ * Errors: BPMF_E_INVALID (model with S > 16 or K > 64, n_slots outside
+ * 1..256, max_nnz outside 1..2^20, max_q outside 1..1024), BPMF_E_HIP. */
+bpmf_status bpmf_server_create_resident(bpmf_server **srv, const bpmf_foldin_model *m, int32_t n_slots,
+                                        int32_t max_nnz, int32_t max_q, int64_t idle_polls);
+
 /* Queues one request (host arrays: nnz column indices in [0, N) and ratings,
  * nq query columns in [0, N)).  BPMF_E_INVALID if an index is out of range or
- * the request alone exceeds one stream's share of the budget. */
+ * the request alone exceeds one stream's share of the budget (resident mode:
+ * the slot size). */
 bpmf_status bpmf_server_submit(bpmf_server *srv, int64_t id, int32_t nnz, const int32_t *h_cols,
                                const float *h_vals, int32_t nq, const int32_t *h_q_cols);
 

@@ -85,6 +85,7 @@ EXPORTS = {
     "bpmf_foldin_workspace_size": [P, I64, P],
     "bpmf_foldin": [P, I64, P, P, P, P, P, I64, P, P, SZ, P],
     "bpmf_server_create": [P, P, SZ, I32, I32, I32],
+    "bpmf_server_create_resident": [P, P, I32, I32, I32, I64],
     "bpmf_server_submit": [P, I64, I32, P, P, I32, P],
     "bpmf_server_poll": [P, I32, P, P, P, I64, P, P],
     "bpmf_server_drain": [P],

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbpmf.so")
 SOURCES = ["bpmf_host.hip", "kernels_f64.hip", "kernels_nw.hip", "kernels_mixed.hip", "kernels_mixed128.hip", "kernels_rank1.hip",
-           "kernels_foldin.hip", "serving.hip"]
+           "kernels_foldin.hip", "kernels_resident.hip", "serving.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

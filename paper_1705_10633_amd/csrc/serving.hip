@@ -9,6 +9,15 @@
 // uploads, kernels and downloads of different batches overlap; a request that
 // arrives while others are on the GPU waits only for the next free slot.
 // Each request's predictions are computed independently of its batch mates.
+//
+// Resident mode (bpmf_server_create_resident): no launch or copy per
+// request.  A persistent kernel (kernels_resident.hip) owns n_slots request
+// slots in coherent pinned host memory; the dispatcher writes a queued
+// request into a free slot and bumps its sequence number, the kernel writes
+// the predictions back into the slot, and the dispatcher collects them.  The
+// kernel ends after about a second without requests (or on the stop flag);
+// the dispatcher launches it again whenever a request waits and it is not
+// running.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -84,6 +93,18 @@ struct bpmf_server {
     int device = 0;
     std::thread worker;
     std::string error;
+    // resident mode
+    bool resident = false;
+    int n_slots = 0, max_nnz = 0, max_q = 0;
+    int64_t idle_polls = 0;
+    size_t r_slot_bytes = 0;
+    char *r_slots = nullptr;          // coherent pinned host memory
+    int32_t *r_stop = nullptr;        // coherent pinned host memory
+    char *r_dev = nullptr;            // device staging
+    hipStream_t r_stream = nullptr;
+    std::vector<Req> r_req;
+    std::vector<int32_t> r_seq;
+    std::vector<char> r_busy;
 };
 
 static bpmf_status srv_fail(bpmf_status s, const std::string &m)
@@ -224,7 +245,184 @@ static void worker_loop(bpmf_server *srv)
     }
 }
 
+// Device staging of the resident server: cols and vals (max_nnz per slot),
+// query columns (max_q per slot), then Lambda_s mu_s (S x K).
+static size_t resident_dev_bytes(int32_t n_slots, int32_t max_nnz, int32_t max_q, int S, int K)
+{
+    return 2 * al(4 * (size_t)n_slots * max_nnz) + al(4 * (size_t)n_slots * max_q) + al(4 * (size_t)S * K);
+}
+
+static float *resident_lam_mu(bpmf_server *srv)
+{
+    return (float *)(srv->r_dev + 2 * al(4 * (size_t)srv->n_slots * srv->max_nnz) +
+                     al(4 * (size_t)srv->n_slots * srv->max_q));
+}
+
+static bpmf::ResidentArgs resident_args(bpmf_server *srv)
+{
+    bpmf::ResidentArgs ra;
+    ra.slots = srv->r_slots;
+    ra.slot_bytes = (int64_t)srv->r_slot_bytes;
+    ra.max_nnz = srv->max_nnz;
+    ra.max_q = srv->max_q;
+    ra.stop = srv->r_stop;
+    ra.dev_cols = (int32_t *)srv->r_dev;
+    ra.dev_vals = (float *)(srv->r_dev + al(4 * (size_t)srv->n_slots * srv->max_nnz));
+    ra.dev_q = (int32_t *)(srv->r_dev + 2 * al(4 * (size_t)srv->n_slots * srv->max_nnz));
+    ra.lam_mu = resident_lam_mu(srv);
+    ra.idle_polls = srv->idle_polls;
+    return ra;
+}
+
+static hipError_t resident_launch(bpmf_server *srv)
+{
+    const bpmf_foldin_model &m = srv->m;
+    return bpmf::launch_resident(srv->n_slots, m.S, m.K, m.N, m.alpha, m.mean_rating, m.d_V, m.d_Lambda, m.d_mu,
+                                 resident_args(srv), srv->r_stream);
+}
+
+static bpmf::ResidentSlotHeader *slot_header(bpmf_server *srv, int i)
+{
+    return (bpmf::ResidentSlotHeader *)(srv->r_slots + (size_t)i * srv->r_slot_bytes);
+}
+
+static void resident_loop(bpmf_server *srv)
+{
+    hipSetDevice(srv->device);
+    int relaunches = 0;  // launches since the last completed request
+    while (true) {
+        bool progress = false, any_busy = false;
+        // completions
+        for (int i = 0; i < srv->n_slots; ++i) {
+            if (!srv->r_busy[i]) continue;
+            bpmf::ResidentSlotHeader *h = slot_header(srv, i);
+            if (__atomic_load_n(&h->done_seq, __ATOMIC_ACQUIRE) != srv->r_seq[i]) {
+                any_busy = true;
+                continue;
+            }
+            const auto t = Clock::now();
+            const float *out = (const float *)((char *)h + bpmf::RESIDENT_HEADER_BYTES +
+                                               8 * (size_t)srv->max_nnz + 4 * (size_t)srv->max_q);
+            Req &r = srv->r_req[i];
+            Done dn;
+            dn.id = r.id;
+            dn.preds.assign(out, out + r.qcols.size());
+            dn.latency = std::chrono::duration<double>(t - r.t_submit).count();
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->done.push_back(std::move(dn));
+            srv->completed += 1;
+            srv->stats.requests_done += 1;
+            srv->inflight -= 1;
+            srv->r_busy[i] = 0;
+            progress = true;
+            relaunches = 0;
+            srv->cv_done.notify_all();
+        }
+        // free slots take queued requests in arrival order
+        for (int i = 0; i < srv->n_slots; ++i) {
+            if (srv->r_busy[i]) continue;
+            {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                if (srv->queue.empty()) break;
+                srv->r_req[i] = std::move(srv->queue.front());
+                srv->queue.pop_front();
+                srv->inflight += 1;
+                srv->stats.batches += 1;
+                srv->stats.max_batch = 1;
+                int64_t busy = 1;
+                for (int k = 0; k < srv->n_slots; ++k) busy += srv->r_busy[k] ? 1 : 0;
+                srv->stats.max_inflight = std::max<int64_t>(srv->stats.max_inflight, busy);
+            }
+            const Req &r = srv->r_req[i];
+            bpmf::ResidentSlotHeader *h = slot_header(srv, i);
+            int32_t *cols = (int32_t *)((char *)h + bpmf::RESIDENT_HEADER_BYTES);
+            float *vals = (float *)(cols + srv->max_nnz);
+            int32_t *qc = (int32_t *)(vals + srv->max_nnz);
+            std::memcpy(cols, r.cols.data(), 4 * r.cols.size());
+            std::memcpy(vals, r.vals.data(), 4 * r.vals.size());
+            std::memcpy(qc, r.qcols.data(), 4 * r.qcols.size());
+            h->nnz = (int32_t)r.cols.size();
+            h->nq = (int32_t)r.qcols.size();
+            srv->r_seq[i] += 1;
+            __atomic_store_n(&h->req_seq, srv->r_seq[i], __ATOMIC_RELEASE);
+            __atomic_fetch_add(srv->r_stop + 1, 1, __ATOMIC_RELEASE);  // activity: no workgroup ends while requests come
+            srv->r_busy[i] = 1;
+            any_busy = true;
+            progress = true;
+        }
+        // a request waits and the kernel has ended (idle timeout): launch it again
+        if (any_busy && hipStreamQuery(srv->r_stream) == hipSuccess) {
+            if (++relaunches > 3 || resident_launch(srv) != hipSuccess) {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                srv->error = "resident fold-in kernel makes no progress";
+                srv->stop = true;
+                srv->cv_done.notify_all();
+                return;
+            }
+        }
+        if (srv->stop) {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (srv->queue.empty() && !any_busy) return;
+        }
+        if (!progress) {
+            if (any_busy) {
+                std::this_thread::yield();
+            } else {
+                std::unique_lock<std::mutex> lk(srv->mu);
+                srv->cv_submit.wait_for(lk, std::chrono::milliseconds(1),
+                                        [&] { return !srv->queue.empty() || srv->stop; });
+            }
+        }
+    }
+}
+
 extern "C" {
+
+bpmf_status bpmf_server_create_resident(bpmf_server **out, const bpmf_foldin_model *m, int32_t n_slots,
+                                        int32_t max_nnz, int32_t max_q, int64_t idle_polls)
+{
+    if (!out || !m) return srv_fail(BPMF_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (m->S < 1 || m->S > 16 || m->K < 1 || m->K > 64 || m->N < 1 || !m->d_V || !m->d_Lambda || !m->d_mu)
+        return srv_fail(BPMF_E_INVALID, "bad fold-in model (resident mode: S in 1..16, K in 1..64)");
+    if (n_slots < 1 || n_slots > 256 || max_nnz < 1 || max_nnz > (1 << 20) || max_q < 1 || max_q > 1024)
+        return srv_fail(BPMF_E_INVALID, "n_slots in 1..256, max_nnz in 1..2^20, max_q in 1..1024");
+    bpmf_server *srv = new (std::nothrow) bpmf_server();
+    if (!srv) return srv_fail(BPMF_E_NOMEM, "server allocation");
+    srv->m = *m;
+    srv->resident = true;
+    srv->n_slots = n_slots;
+    srv->max_nnz = max_nnz;
+    srv->max_q = max_q;
+    srv->idle_polls = idle_polls > 0 ? idle_polls : 500000;
+    srv->r_slot_bytes = al(bpmf::RESIDENT_HEADER_BYTES + 8 * (size_t)max_nnz + 8 * (size_t)max_q);
+    srv->r_req.resize(n_slots);
+    srv->r_seq.assign(n_slots, 0);
+    srv->r_busy.assign(n_slots, 0);
+    srv->max_batch = 1;
+    srv->max_inflight = n_slots;
+    srv->stats.stream_capacity = (int64_t)srv->r_slot_bytes;
+    const size_t dev_bytes = resident_dev_bytes(n_slots, max_nnz, max_q, m->S, m->K);
+    if (hipGetDevice(&srv->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&srv->r_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc((void **)&srv->r_slots, srv->r_slot_bytes * n_slots, hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc((void **)&srv->r_stop, kAlign, hipHostMallocCoherent) != hipSuccess ||
+        hipMalloc((void **)&srv->r_dev, dev_bytes) != hipSuccess ||
+        bpmf::prepare_resident(m->S, m->K, m->d_Lambda, m->d_mu, resident_lam_mu(srv), srv->r_stream) != hipSuccess ||
+        hipStreamSynchronize(srv->r_stream) != hipSuccess) {
+        bpmf_server_destroy(srv);
+        return srv_fail(BPMF_E_HIP, "resident server allocation failed");
+    }
+    std::memset(srv->r_slots, 0, srv->r_slot_bytes * n_slots);
+    std::memset(srv->r_stop, 0, kAlign);
+    if (resident_launch(srv) != hipSuccess) {
+        bpmf_server_destroy(srv);
+        return srv_fail(BPMF_E_HIP, "resident kernel launch failed");
+    }
+    srv->worker = std::thread(resident_loop, srv);
+    *out = srv;
+    return BPMF_OK;
+}
 
 bpmf_status bpmf_server_create(bpmf_server **out, const bpmf_foldin_model *m, size_t mem_budget_bytes,
                                int32_t n_streams, int32_t max_batch, int32_t max_inflight)
@@ -274,8 +472,12 @@ bpmf_status bpmf_server_submit(bpmf_server *srv, int64_t id, int32_t nnz, const 
         if (h_cols[i] < 0 || h_cols[i] >= srv->m.N) return srv_fail(BPMF_E_INVALID, "rating column out of range");
     for (int32_t i = 0; i < nq; ++i)
         if (h_q_cols[i] < 0 || h_q_cols[i] >= srv->m.N) return srv_fail(BPMF_E_INVALID, "query column out of range");
-    if (batch_bytes(1, nnz, nq, srv->m.S) > srv->capacity)
+    if (srv->resident) {
+        if (nnz > srv->max_nnz || nq > srv->max_q)
+            return srv_fail(BPMF_E_INVALID, "request exceeds the slot size (max_nnz, max_q)");
+    } else if (batch_bytes(1, nnz, nq, srv->m.S) > srv->capacity) {
         return srv_fail(BPMF_E_INVALID, "request exceeds one stream's memory budget");
+    }
     Req r;
     r.id = id;
     r.cols.assign(h_cols, h_cols + nnz);
@@ -389,6 +591,14 @@ bpmf_status bpmf_server_destroy(bpmf_server *srv)
     }
     srv->cv_submit.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
+    if (srv->r_stop) __atomic_store_n(srv->r_stop, 1, __ATOMIC_RELEASE);
+    if (srv->r_stream) {
+        hipStreamSynchronize(srv->r_stream);
+        hipStreamDestroy(srv->r_stream);
+    }
+    if (srv->r_dev) hipFree(srv->r_dev);
+    if (srv->r_slots) hipHostFree(srv->r_slots);
+    if (srv->r_stop) hipHostFree(srv->r_stop);
     for (auto &sl : srv->slots) {
         if (sl.stream) hipStreamSynchronize(sl.stream);
         if (sl.done) hipEventDestroy(sl.done);

@@ -17,11 +17,17 @@ class FoldinServer:
     (a sampler.Foldin holding the device arrays)."""
 
     def __init__(self, foldin, mem_budget_bytes=256 << 20, n_streams=4, max_batch=256,
-                 max_inflight=4096):
+                 max_inflight=4096, resident=False, n_slots=32, max_nnz=5000, max_q=128, idle_polls=0):
+        """resident=True: one persistent kernel serves n_slots requests at a
+        time (bpmf_server_create_resident) instead of a launch per batch."""
         self.foldin = foldin  # keeps the model's device arrays alive
         self.srv = C.c_void_p()
-        call("bpmf_server_create", C.byref(self.srv), C.byref(foldin.model), C.c_size_t(mem_budget_bytes),
-             n_streams, max_batch, max_inflight)
+        if resident:
+            call("bpmf_server_create_resident", C.byref(self.srv), C.byref(foldin.model), n_slots, max_nnz,
+                 max_q, int(idle_polls))
+        else:
+            call("bpmf_server_create", C.byref(self.srv), C.byref(foldin.model), C.c_size_t(mem_budget_bytes),
+                 n_streams, max_batch, max_inflight)
 
     def close(self):
         if self.srv:
