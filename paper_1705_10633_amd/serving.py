@@ -83,8 +83,11 @@ class FoldinServer:
 
 
 def bench_foldin(seconds=2.0, rates=(5000, 10000, 20000, 50000), S=16, N=20000, K=64, Q=100,
-                 n_streams=4, mem_budget=256 << 20, max_batch=256, log=print):
-    """p50 / p99 latency of Poisson request streams against S stored samples."""
+                 n_streams=4, mem_budget=256 << 20, max_batch=256, log=print, resident_rate=20000,
+                 saturating_batch=4096):
+    """p50 / p99 latency of Poisson request streams against S stored samples
+    (batched server at each rate, the resident-kernel server at one), and the
+    fold-in kernel's FP32 work rate on one saturating batch."""
     from . import synth
     from .sampler import Foldin
     model = synth.foldin_model(S=S, N=N, K=K)
@@ -117,4 +120,52 @@ def bench_foldin(seconds=2.0, rates=(5000, 10000, 20000, 50000), S=16, N=20000, 
         out["rates"][str(rate)] = rec
         log(f"[serve] {rate:6d} req/s: p50 {rec['p50_ms']:.3f} ms p99 {rec['p99_ms']:.3f} ms "
             f"(mean batch {rec['mean_batch']:.1f}, achieved {rec['achieved_rps']:.0f} req/s, gen {gen:.1f} s)")
+    if resident_rate:
+        n = int(resident_rate * seconds)
+        req = synth.foldin_requests(n, N, seed=105, Q=Q, rate=resident_rate, stream_offset=resident_rate)
+        srv = FoldinServer(fm, resident=True, n_slots=32, max_nnz=5000, max_q=Q)
+        srv.replay(synth.foldin_requests(64, N, seed=7, Q=Q, rate=resident_rate, stream_offset=1))
+        _, lat = srv.replay(req)
+        srv.close()
+        lat_ms = lat * 1e3
+        out["resident"] = {"rate": resident_rate, "slots": 32, "requests": n,
+                           "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99))}
+        log(f"[serve] resident kernel, {resident_rate} req/s: p50 {out['resident']['p50_ms']:.3f} ms "
+            f"p99 {out['resident']['p99_ms']:.3f} ms")
+    if saturating_batch:
+        out["saturating_batch"] = foldin_batch_throughput(fm, N, K, S, Q, saturating_batch)
+        sb = out["saturating_batch"]
+        log(f"[serve] batch of {saturating_batch}: {sb['ms_per_batch']:.3f} ms, {sb['requests_per_s']:.3g} req/s, "
+            f"{sb['achieved_TFLOPs']:.2f} TFLOP/s = {100 * sb['frac']:.1f} % of FP32 peak")
     return out
+
+
+def foldin_batch_throughput(fm, N, K, S, Q, n_req, reps=10, seed=106):
+    """One bpmf_foldin call over n_req requests, timed with HIP events on the
+    launch stream; algorithmic FP32 work per (request, sample): the Gram and
+    rhs nnz (K^2 + 3K), the Cholesky K^3 / 3, the two solves 2 K^2 and the
+    query dot products 2 K Q."""
+    import torch
+    from . import synth
+    req = synth.foldin_requests(n_req, N, seed=seed, Q=Q)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    args = [dev(req.ptr), dev(req.cols), dev(req.vals), dev(req.q_ptr), dev(req.q_cols)]
+    out = torch.empty(max(int(req.q_cols.size), 1), dtype=torch.float32, device="cuda")
+    ws = torch.empty(fm.workspace_bytes(int(req.q_cols.size)), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        fm.run(*args, out=out, ws=ws, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fm.run(*args, out=out, ws=ws, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nnz = np.diff(req.ptr).astype(np.float64)
+    nq = np.diff(req.q_ptr).astype(np.float64)
+    flops = S * float(np.sum(nnz * (K * K + 3 * K) + K ** 3 / 3.0 + 2 * K * K + 2 * K * nq))
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"requests": n_req, "ms_per_batch": ms, "requests_per_s": n_req / (ms * 1e-3),
+            "algorithmic_flop_per_batch": flops, "achieved_TFLOPs": tf, "peak_TFLOPs": 157.3,
+            "frac": tf / 157.3, "bound": "alu"}
