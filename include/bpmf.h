@@ -284,7 +284,8 @@ bpmf_status bpmf_server_create(bpmf_server **srv, const bpmf_foldin_model *m,
  * request waits.  submit / poll / drain / replay / stats / destroy work as in
  * batching mode; stats count each request as a batch of one.
  * Errors: BPMF_E_INVALID (model with S > 16 or K > 64, n_slots outside
- * 1..256, max_nnz outside 1..2^20, max_q outside 1..1024), BPMF_E_HIP. */
+ * 1..256 or above the slot workgroups the device holds at once, max_nnz
+ * outside 1..2^20, max_q outside 1..1024), BPMF_E_HIP. */
 bpmf_status bpmf_server_create_resident(bpmf_server **srv, const bpmf_foldin_model *m, int32_t n_slots,
                                         int32_t max_nnz, int32_t max_q, int64_t idle_polls);
 

@@ -203,6 +203,10 @@ struct ResidentArgs {
 size_t resident_lds_bytes(int K, int S);
 // Forms lam_mu (S x K) on stream st and sets the kernel's LDS limit.
 hipError_t prepare_resident(int S, int K, const double *Lam, const double *mu, float *lam_mu, hipStream_t st);
+// Slot workgroups the device holds at once (after prepare_resident); every
+// slot's workgroup must be resident, or its requests could wait as long as
+// the other slots stay busy.
+hipError_t resident_max_slots(int K, int S, int *max_slots);
 hipError_t launch_resident(int n_slots, int S, int K, int64_t N, double alpha, double rbar, const float *Vs,
                            const double *Lam, const double *mu, const ResidentArgs &ra, hipStream_t st);
 hipError_t launch_to_bf16(const float *X, int64_t n, int K, int stride, uint16_t *out,

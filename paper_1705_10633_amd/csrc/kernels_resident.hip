@@ -191,6 +191,20 @@ hipError_t prepare_resident(int S, int K, const double *Lam, const double *mu, f
                                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+hipError_t resident_max_slots(int K, int S, int *max_slots)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const size_t lds = resident_lds_bytes(K, S);
+    e = K <= 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_foldin_kernel<32>, 64 * S, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_foldin_kernel<64>, 64 * S, lds);
+    if (e != hipSuccess) return e;
+    *max_slots = per_cu * cus;
+    return hipSuccess;
+}
+
 hipError_t launch_resident(int n_slots, int S, int K, int64_t N, double alpha, double rbar, const float *Vs,
                            const double *Lam, const double *mu, const ResidentArgs &ra, hipStream_t st)
 {

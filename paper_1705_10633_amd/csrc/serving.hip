@@ -413,6 +413,16 @@ bpmf_status bpmf_server_create_resident(bpmf_server **out, const bpmf_foldin_mod
         bpmf_server_destroy(srv);
         return srv_fail(BPMF_E_HIP, "resident server allocation failed");
     }
+    int max_slots = 0;
+    if (bpmf::resident_max_slots(m->K, m->S, &max_slots) != hipSuccess) {
+        bpmf_server_destroy(srv);
+        return srv_fail(BPMF_E_HIP, "resident kernel occupancy query failed");
+    }
+    if (n_slots > max_slots) {
+        bpmf_server_destroy(srv);
+        return srv_fail(BPMF_E_INVALID, "n_slots exceeds the slot workgroups the device holds at once (" +
+                                            std::to_string(max_slots) + " for this S and K)");
+    }
     std::memset(srv->r_slots, 0, srv->r_slot_bytes * n_slots);
     std::memset(srv->r_stop, 0, kAlign);
     if (resident_launch(srv) != hipSuccess) {

@@ -68,6 +68,28 @@ def test_resident_empty_request_and_slot_admission():
     assert np.array_equal(got[0], _run_direct(fm, one))
 
 
+def test_resident_server_with_a_slot_per_compute_unit():
+    """256 slots of 16 wavefronts: one slot workgroup per CU of the chip (the
+    most the device holds at once, else creation is refused)."""
+    from paper_1705_10633_amd.serving import FoldinServer
+    from paper_1705_10633_amd._lib import BpmfError
+    model = synth.foldin_model(S=16, N=3000, K=64, seed=9)
+    fm = _foldin(model)
+    req = synth.foldin_requests(300, 3000, seed=9, Q=16, cap=400)
+    try:
+        srv = FoldinServer(fm, resident=True, n_slots=256, max_nnz=400, max_q=16, idle_polls=20000)
+    except BpmfError as e:
+        assert "holds at once" in str(e)
+        pytest.skip("device holds fewer than 256 slot workgroups")
+    _submit_all(srv, req)
+    srv.drain()
+    got = _collect(srv, req.n)
+    srv.close()
+    ref = _run_direct(fm, req)
+    for i in range(req.n):
+        assert np.array_equal(got[i], ref[req.q_ptr[i]:req.q_ptr[i + 1]]), i
+
+
 def test_resident_kernel_ends_when_idle_and_is_relaunched():
     """With a short idle limit the kernel ends between the two bursts; the
     second burst is served by a new launch with the same results."""
