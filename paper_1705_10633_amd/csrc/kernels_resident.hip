@@ -23,7 +23,7 @@
 // which the server assigned no request to any slot (about a microsecond each
 // with the sleep between them); the host relaunches the kernel when a request
 // is pending and the kernel has ended.
-#include "common.hpp"
+#include "resident.hpp"
 #include "rowsolve.hpp"
 
 namespace bpmf {

@@ -32,7 +32,7 @@
 #include <vector>
 
 #include "../../include/bpmf.h"
-#include "common.hpp"
+#include "resident.hpp"
 
 namespace {
 
