@@ -100,9 +100,21 @@ def measured_traffic():
         fields.get("fetch_scale", "?"), fields.get("write_scale", "?"))
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def time_sweeps(sampler, steps, warmup):
     import torch
-    sampler.sweep(warmup)
+    if warmup > 0:
+        sampler.sweep(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -136,6 +148,14 @@ def cpu_baseline(prob, n_sweeps=3, seed=2024, budget_s=15.0):
                 "sample": f"{n_sweeps} whole FP64 oracle sweeps of the full workload (both halves, both "
                           f"Normal-Wishart steps and {prob.test_rows.size} held-out predictions per sweep): "
                           f"{rows} rows in {t:.1f} s wall on {nth} threads"}
+    return row_sample(prob, nth, budget_s, seed, flops)
+
+
+def row_sample(prob, nth, budget_s, seed, flops):
+    """Oracle row updates of a uniform sample of the rows of both halves of one
+    sweep, sized to about budget_s on nth threads."""
+    from oracle import oracle as O
+    R, K = prob.R, prob.K
     frac = min(1.0, max(1e-4, budget_s / (flops / (4e9 * nth))))
     rng = np.random.default_rng(seed)
     Lam = np.eye(K) * 2.0
@@ -164,7 +184,7 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="movielens",
                     help="synthetic workload (the metric is quoted on movielens)")
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -215,6 +235,11 @@ def main():
         print(json.dumps({"metric": f"Gibbs rows sampled/sec at K={K}", "value": value, "ms_per_step": ms_wall,
                           "workload": args.workload}))
         return
+
+    # four more runs of the same number of sweeps, for the spread between runs
+    runs = [ms_wall] + [time_sweeps(s, args.steps, 0)[1] for _ in range(4)]
+    log(f"[bench] five runs of {args.steps} sweeps: " + " ".join(f"{r:.3f}" for r in runs) +
+        f" ms/sweep (median {float(np.median(runs)):.3f})")
 
     # per-kernel durations over the same number of sweeps, events on the launch stream
     s.set_timing(True)
@@ -274,11 +299,18 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob)
         log(f"[bench] cpu baseline: {cpu['value']:.4g} rows/s ({cpu['sample']})")
+        R = prob.R
+        one = row_sample(prob, 1, 4.0, 2025, 2.0 * R.nnz * K * K + (R.M + R.N) * K ** 3 / 3.0)
+        cpu["value_1core"] = one["value"]
+        cpu["sample_1core"] = one["sample"]
+        cpu["host_cpu"] = host_cpu_model()
+        log(f"[bench] cpu baseline, one thread: {one['value']:.4g} rows/s ({one['sample']}); host {cpu['host_cpu']}")
 
     out = {
         "metric": "Gibbs rows sampled/sec at K=64 (vs plain FP64 path) + p50/p99 fold-in latency",
         "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": ms_wall, "ms_per_step_runs": runs, "ms_per_step_median_of_runs": float(np.median(runs)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": prec if K <= 64 else "f64", "data": "synthetic",
         "config": {"workload": wl["text"],
                    "M": prob.M, "N": prob.N, "nnz": prob.R.nnz, "K": K,
