@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every candidate launch shape first and sweep with the fastest")
     ap.add_argument("--only-timed", action="store_true",
                     help="run only warm-up and timed sweeps (for profiler runs)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -222,10 +224,22 @@ def main():
         f"nnz={prob.R.nnz} K={K} ({prob.note})")
 
     R32 = DeviceRatings(prob.R, val_dtype="float32")
+    shape, tune_table = {}, None
+    if args.autotune:
+        from paper_1705_10633_amd import autotune
+        t0 = time.perf_counter()
+        shape, tune_table = autotune.tune(
+            R32, K, prob.U0.astype(np.float32), prob.V0.astype(np.float32),
+            [prob.R.row_counts(), prob.R.col_counts()], precision=prec, sweeps=args.steps, warmup=3,
+            alpha=prob.alpha, beta0=prob.beta0, nu0=prob.nu0, mean_rating=prob.mean_rating, seed=2024)
+        for c, ms in tune_table:
+            log(f"[bench] autotune {ms:8.3f} ms/sweep  {c}")
+        log(f"[bench] autotune: {len(tune_table)} shapes in {time.perf_counter() - t0:.1f} s, "
+            f"kept {shape}")
     s = Sampler(R32, K, prob.U0.astype(np.float32), prob.V0.astype(np.float32), precision=prec,
                 alpha=prob.alpha, beta0=prob.beta0, nu0=prob.nu0, mean_rating=prob.mean_rating,
                 seed=2024, burnin=0, test_rows=prob.test_rows, test_cols=prob.test_cols,
-                use_graph=True)
+                use_graph=True, shape=shape)
     rows_per_sweep = prob.M + prob.N
     ms_dev, ms_wall = time_sweeps(s, args.steps, args.warmup)
     value = rows_per_sweep / (ms_wall * 1e-3)
@@ -233,7 +247,9 @@ def main():
         f"-> {value:.4g} rows/s")
     if args.only_timed:
         print(json.dumps({"metric": f"Gibbs rows sampled/sec at K={K}", "value": value, "ms_per_step": ms_wall,
-                          "workload": args.workload}))
+                          "workload": args.workload, "launch_shape": shape,
+                          "autotune": None if tune_table is None else
+                          [{"shape": c, "ms_per_sweep": ms} for c, ms in tune_table]}))
         return
 
     # four more runs of the same number of sweeps, for the spread between runs
@@ -325,7 +341,12 @@ def main():
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
         "serving": serving,
+        "launch_shape": shape,
     }
+    if tune_table is not None:
+        # with a non-built-in shape some rows run in the rank-one or piece launches, which the
+        # roofline's two row launches then no longer hold
+        out["autotune"] = [{"shape": c, "ms_per_sweep": ms} for c, ms in tune_table]
     print(json.dumps(out))
 
 

@@ -85,6 +85,35 @@ typedef struct {
     int32_t val_is_f64;
 } bpmf_ratings;
 
+/* Launch shape of the mixed-precision sweep (FP32/BF16 modes, K <= 64):
+ * how the rating-count-ordered row table is cut into launches.  Rows are
+ * independent given the hyper-parameters (Section 3.1), so every shape samples
+ * the same conditional; shapes differ only in summation order (pieces of a
+ * heavy row are summed piece by piece) and in whether a row with few ratings
+ * takes rank-one updates of chol(Lambda) instead of a fresh factorisation
+ * (Section 3.1), i.e. within FP32 rounding.  A field of 0 keeps the built-in
+ * choice.  Read once by bpmf_init; ignored in BPMF_FP64 and for K > 64.
+ *   heavy_min_ratings  rows with at least this many ratings are cut into
+ *                      pieces (0: 2048; else >= 64)
+ *   piece_min_ratings  shortest piece (0: 512; else >= 64)
+ *   heavy_split        1: always cut heavy rows, -1: never, 0: only when they
+ *                      hold >= 10% of the ratings
+ *   rank1_max_ratings  rows with at most this many ratings take the rank-one
+ *                      kernels (0: 3 for K <= 32, 2 for K <= 64; -1: none;
+ *                      else 1..4)
+ *   rank1_split        1: always use the rank-one launch when such rows exist,
+ *                      -1: never, 0: only when they are >= 16384 rows or
+ *                      >= 1/16 of the side
+ * Out-of-range fields make bpmf_workspace_size and bpmf_init return
+ * BPMF_E_INVALID. */
+typedef struct {
+    int32_t heavy_min_ratings;
+    int32_t piece_min_ratings;
+    int32_t heavy_split;
+    int32_t rank1_max_ratings;
+    int32_t rank1_split;
+} bpmf_launch_shape;
+
 /* Model and run parameters (Section 2: Gaussian rows, Normal-Wishart hyperpriors).
  *   K          latent dimension, 1..128
  *   precision  bpmf_precision
@@ -96,7 +125,9 @@ typedef struct {
  *   burnin     sweeps before test predictions are averaged
  *   use_graph  1 = replay whole sweeps from a captured HIP graph (Philox mode)
  *   validate   1 = copy CSR/CSC to the host at init and check the structure
- *              (monotone pointers, sorted unique in-range indices, CSR == CSC) */
+ *              (monotone pointers, sorted unique in-range indices, CSR == CSC)
+ *   shape      optional launch shape (host pointer, NULL = built-in choices),
+ *              read during the call */
 typedef struct {
     int32_t K;
     int32_t precision;
@@ -110,6 +141,7 @@ typedef struct {
     int32_t burnin;
     int32_t use_graph;
     int32_t validate;
+    const bpmf_launch_shape *shape;
 } bpmf_params;
 
 typedef struct bpmf_ctx bpmf_ctx;

@@ -30,10 +30,16 @@ class Ratings(C.Structure):
                 ("val_is_f64", I32)]
 
 
+class LaunchShape(C.Structure):
+    _fields_ = [("heavy_min_ratings", I32), ("piece_min_ratings", I32), ("heavy_split", I32),
+                ("rank1_max_ratings", I32), ("rank1_split", I32)]
+
+
 class Params(C.Structure):
     _fields_ = [("K", I32), ("precision", I32), ("alpha", F64), ("beta0", F64), ("nu0", F64),
                 ("mu0", P), ("W0", P), ("mean_rating", F64), ("seed", C.c_uint64),
-                ("burnin", I32), ("use_graph", I32), ("validate", I32)]
+                ("burnin", I32), ("use_graph", I32), ("validate", I32),
+                ("shape", C.POINTER(LaunchShape))]
 
 
 class Info(C.Structure):

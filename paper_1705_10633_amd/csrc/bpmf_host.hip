@@ -93,6 +93,24 @@ static int64_t rank1_limit(int K)
     return std::min<int64_t>(lim, rank1_max_ratings());
 }
 
+// The launch shape with the built-in choices filled in for the fields left at 0.
+struct LaunchShape {
+    int64_t heavy_min, piece_min, rank1_max;
+    int heavy_split, rank1_split;
+};
+
+static LaunchShape resolve_shape(const bpmf_launch_shape *sh, int K)
+{
+    LaunchShape r{heavy_min_ratings(), 512, rank1_limit(K), 0, 0};
+    if (!sh) return r;
+    if (sh->heavy_min_ratings) r.heavy_min = sh->heavy_min_ratings;
+    if (sh->piece_min_ratings) r.piece_min = sh->piece_min_ratings;
+    if (sh->rank1_max_ratings) r.rank1_max = sh->rank1_max_ratings < 0 ? 0 : sh->rank1_max_ratings;
+    r.heavy_split = sh->heavy_split;
+    r.rank1_split = sh->rank1_split;
+    return r;
+}
+
 static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_test)
 {
     Offsets o;
@@ -227,6 +245,17 @@ static bpmf_status check_params(const bpmf_ratings *R, const bpmf_params *p)
     if (!(p->nu0 > p->K - 1) || !std::isfinite(p->nu0)) return fail(BPMF_E_INVALID, "nu0 must be > K - 1");
     if (!p->mu0 || !p->W0) return fail(BPMF_E_INVALID, "mu0 and W0 are required");
     if (p->burnin < 0) return fail(BPMF_E_INVALID, "burnin must be >= 0");
+    if (const bpmf_launch_shape *sh = p->shape) {
+        if (sh->heavy_min_ratings != 0 && sh->heavy_min_ratings < 64)
+            return fail(BPMF_E_INVALID, "shape.heavy_min_ratings must be 0 or >= 64");
+        if (sh->piece_min_ratings != 0 && sh->piece_min_ratings < 64)
+            return fail(BPMF_E_INVALID, "shape.piece_min_ratings must be 0 or >= 64");
+        if (sh->heavy_split < -1 || sh->heavy_split > 1 || sh->rank1_split < -1 || sh->rank1_split > 1)
+            return fail(BPMF_E_INVALID, "shape.heavy_split and shape.rank1_split must be -1, 0 or 1");
+        if (sh->rank1_max_ratings < -1 || sh->rank1_max_ratings > rank1_max_ratings())
+            return fail(BPMF_E_INVALID, "shape.rank1_max_ratings must be -1, 0 or 1.." +
+                                            std::to_string(rank1_max_ratings()));
+    }
     if (R->M < 1 || R->N < 1 || R->nnz < 0) return fail(BPMF_E_INVALID, "M, N must be >= 1, nnz >= 0");
     if (R->M > INT32_MAX || R->N > INT32_MAX) return fail(BPMF_E_INVALID, "M and N must fit in int32");
     if (!R->d_row_ptr || !R->d_col_ptr) return fail(BPMF_E_INVALID, "NULL row_ptr/col_ptr");
@@ -408,6 +437,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
     }
     c->rbar = rbar;
 
+    const LaunchShape shape = resolve_shape(p->shape, K);
     // row order: rating count descending, ties by index
     for (int sd = 0; sd < 2; ++sd) {
         std::vector<int32_t> ord(n[sd]);
@@ -424,7 +454,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         };
         int64_t nh = 0, ns = 0, nt = 0;
         if (c->hyp[sd].Lchol) {
-            const int64_t lim = rank1_limit(K);
+            const int64_t lim = shape.rank1_max;
             int64_t m = 0, t = 0;
             while (m < n[sd] && pp[ord[n[sd] - 1 - m] + 1] - pp[ord[n[sd] - 1 - m]] <= lim) {
                 if (pp[ord[n[sd] - 1 - m] + 1] - pp[ord[n[sd] - 1 - m]] <= 1) ++t;
@@ -432,7 +462,10 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
             }
             // a short tail finishes inside the full kernel's launch anyway;
             // a separate launch pays off once it is a sizeable share of the rows
-            if (m >= 16384 || 16 * m >= n[sd]) {
+            const bool small_launch = shape.rank1_split > 0 ? m > 0
+                                      : (shape.rank1_split == 0 && (m >= 16384 || 16 * m >= n[sd]));
+            if (!small_launch) m = 0;
+            if (small_launch) {
                 ns = m;
                 nt = K <= 32 ? t : 0;
             }
@@ -440,11 +473,11 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
             // sizeable share of the ratings (otherwise they finish inside
             // the one-wavefront launch anyway)
             int64_t hv = 0, hnnz = 0;
-            while (hv < n[sd] - m && hv < kMaxPieces / 2 && pp[ord[hv] + 1] - pp[ord[hv]] >= heavy_min_ratings()) {
+            while (hv < n[sd] - m && hv < kMaxPieces / 2 && pp[ord[hv] + 1] - pp[ord[hv]] >= shape.heavy_min) {
                 hnnz += pp[ord[hv] + 1] - pp[ord[hv]];
                 ++hv;
             }
-            if (10 * hnnz >= R->nnz) nh = hv;
+            if (shape.heavy_split > 0 || (shape.heavy_split == 0 && 10 * hnnz >= R->nnz)) nh = hv;
             c->n_small[sd] = ns;
             c->n_tiny[sd] = nt;
         }
@@ -453,7 +486,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
             int64_t hnnz = 0;
             for (int64_t q = 0; q < nh; ++q) hnnz += pp[ord[q] + 1] - pp[ord[q]];
             // sum over rows of ceil(nnz / psz) <= hnnz / psz + nh <= kMaxPieces
-            const int64_t psz = std::max<int64_t>(512, (hnnz + kMaxPieces - nh - 1) / (kMaxPieces - nh));
+            const int64_t psz = std::max<int64_t>(shape.piece_min, (hnnz + kMaxPieces - nh - 1) / (kMaxPieces - nh));
             for (int64_t q = 0; q < nh; ++q) {
                 const int64_t b = pp[ord[q]], e = pp[ord[q] + 1];
                 ctab.push_back(make_int4(ord[q], (int)tab.size(), 0, 0));

@@ -57,7 +57,7 @@ class Sampler:
                  alpha: float = 2.0, beta0: float = 2.0, nu0: Optional[float] = None,
                  mu0=None, W0=None, mean_rating: float = float("nan"), seed: int = 0,
                  burnin: int = 0, test_rows=None, test_cols=None, use_graph: bool = False,
-                 validate: bool = False, stream=None):
+                 validate: bool = False, stream=None, shape: Optional[dict] = None):
         torch = _torch()
         self.torch = torch
         self.R = ratings
@@ -74,6 +74,12 @@ class Sampler:
         self.params = _lib.Params(K, prec, alpha, beta0, nu0, self._mu0.ctypes.data,
                                   self._W0.ctypes.data, mean_rating, seed, burnin,
                                   1 if use_graph else 0, 1 if validate else 0)
+        # launch shape of the mixed-precision sweep (bpmf_launch_shape); fields left out keep
+        # the library's built-in choice
+        self.shape = dict(shape or {})
+        if shape:
+            self._shape = _lib.LaunchShape(**self.shape)
+            self.params.shape = C.pointer(self._shape)
         self._rs = ratings.cstruct()
         if test_rows is not None:
             self.test_rows = torch.as_tensor(np.asarray(test_rows, np.int32), device="cuda")

@@ -6,7 +6,7 @@ from paper_1705_10633_amd import synth
 
 
 def make_sampler(prob, precision="fp64", val_dtype=None, seed=0, use_graph=False, validate=True,
-                 with_test=True, rbar=None):
+                 with_test=True, rbar=None, shape=None):
     import torch  # noqa: F401
     from paper_1705_10633_amd.sampler import DeviceRatings, Sampler
     if val_dtype is None:
@@ -21,7 +21,7 @@ def make_sampler(prob, precision="fp64", val_dtype=None, seed=0, use_graph=False
                 mean_rating=prob.mean_rating if rbar is None else rbar, seed=seed,
                 burnin=prob.burnin, test_rows=prob.test_rows if with_test else None,
                 test_cols=prob.test_cols if with_test else None, use_graph=use_graph,
-                validate=validate)
+                validate=validate, shape=shape)
     return s
 
 

@@ -2,6 +2,7 @@
 by libbpmf.so, and the host-side validation of parameters returns the
 documented status codes (these calls never touch the device)."""
 import ctypes as C
+import json
 import math
 import os
 import re
@@ -138,3 +139,39 @@ def test_foldin_and_server_argument_checks(lib):
     assert lib.bpmf_server_create(C.byref(srv), C.byref(bad), 1 << 20, 2, 8, 8) == 1
     assert lib.bpmf_server_create(C.byref(srv), C.byref(m), 1 << 20, 0, 8, 8) == 1     # no streams
     assert lib.bpmf_server_create(C.byref(srv), C.byref(m), 64, 1, 8, 8) == 1          # budget too small
+
+
+def test_launch_shape_fields_are_validated(lib):
+    """bpmf_launch_shape: 0 keeps the built-in choice; out-of-range fields
+    are rejected before any device work."""
+    from paper_1705_10633_amd import _lib
+    R = _ratings()
+    good = [{}, {"heavy_min_ratings": 64, "piece_min_ratings": 64, "heavy_split": 1},
+            {"heavy_split": -1, "rank1_max_ratings": -1}, {"rank1_max_ratings": 4, "rank1_split": 1},
+            {"rank1_split": -1}]
+    bad = [{"heavy_min_ratings": 63}, {"heavy_min_ratings": -5}, {"piece_min_ratings": 1},
+           {"heavy_split": 2}, {"rank1_split": -2}, {"rank1_max_ratings": 5},
+           {"rank1_max_ratings": -2}]
+    for fields, want in [(f, 0) for f in good] + [(f, 1) for f in bad]:
+        p, keep = _params(precision=2)
+        shp = _lib.LaunchShape(**fields)
+        p.shape = C.pointer(shp)
+        assert _ws(lib, R, p)[0] == want, fields
+        if want:
+            assert b"shape." in lib.bpmf_last_error()
+
+
+def test_autotune_candidates_follow_the_counts():
+    """The tuner varies only the knobs that change this matrix's launches,
+    puts the built-in choice first, and lists no shape twice."""
+    from paper_1705_10633_amd.autotune import candidate_shapes
+    plain = candidate_shapes([np.full(100, 50), np.full(40, 125)], 64)
+    assert plain == [{}, {"heavy_split": -1, "rank1_max_ratings": -1}]
+    mixed = candidate_shapes([np.array([1, 2, 3, 9000, 50]), np.array([700, 20])], 32)
+    assert mixed[0] == {}
+    assert len(mixed) == len({json.dumps(c, sort_keys=True) for c in mixed})
+    assert {"heavy_split": 1, "heavy_min_ratings": 4096, "piece_min_ratings": 256,
+            "rank1_max_ratings": 3, "rank1_split": 1} in mixed
+    assert not any(c.get("rank1_max_ratings") == 4 for c in mixed)   # no row has 4 ratings
+    assert all(c.get("heavy_min_ratings", 0) <= 9000 for c in mixed)
+    assert candidate_shapes([np.array([1, 9000])], 100) == [{}]     # K > 64: one launch shape

@@ -1,0 +1,77 @@
+"""Launch shapes (bpmf_launch_shape) and the autotuner that picks one.
+
+Every shape cuts the same rows into different launches, so every shape must
+meet the mixed-precision bounds against the FP64 oracle on the same state and
+draws; the tuner must return one of the shapes it timed."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1705_10633_amd import synth
+
+from .gpu_common import make_sampler, row_rel_err, tape_for
+from .test_gpu_parity import MIXED_TOL, _dev, _f32_start
+
+pytestmark = pytest.mark.gpu
+
+
+def _skewed(K, seed):
+    """Six users rate 1100..3000 of 3000 movies, 300 rate 0..4, 200 rate 10..29."""
+    rng = np.random.default_rng(seed)
+    M, N = 506, 3000
+    counts = np.concatenate([rng.integers(1100, N + 1, 6), rng.integers(0, 5, 300), rng.integers(10, 30, 200)])
+    rows = np.repeat(np.arange(M), counts)
+    cols = np.concatenate([rng.choice(N, c, replace=False) for c in counts]).astype(np.int64)
+    vals = 3.0 + rng.standard_normal(rows.size)
+    R = synth.from_coo(M, N, rows, cols, vals)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    return synth.Problem("skewed", R, K, 2.0, np.zeros(K), 2.0, float(K), np.eye(K), 1, 0,
+                         f32(0.3 * rng.standard_normal((M, K))), f32(0.3 * rng.standard_normal((N, K))),
+                         np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), 0, float(vals.mean()))
+
+
+SHAPES = [
+    {},
+    {"heavy_split": 1, "heavy_min_ratings": 1024, "piece_min_ratings": 64},
+    {"heavy_split": -1, "rank1_max_ratings": -1},
+    {"rank1_max_ratings": 4, "rank1_split": 1},
+    {"heavy_split": 1, "heavy_min_ratings": 2048, "piece_min_ratings": 1024, "rank1_max_ratings": 1,
+     "rank1_split": 1},
+]
+
+
+@pytest.mark.parametrize("precision,K", [("fp32", 32), ("fp32", 64), ("bf16", 64)])
+def test_every_launch_shape_meets_the_oracle(precision, K):
+    prob = _f32_start(_skewed(K, seed=K + 11))
+    tape = tape_for(prob, 1, seed=K + 13)
+    ref = O.gibbs(prob, tape, n_sweeps=1, nthreads=8)
+    med, mx = MIXED_TOL[precision]
+    import torch
+    for shape in SHAPES:
+        s = make_sampler(prob, precision=precision, with_test=False, shape=shape)
+        s.sweep(1, tape=_dev(tape))
+        torch.cuda.synchronize()
+        eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+        ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+        print(f"{precision} K={K} {shape}: U median {np.median(eu):.2e} max {eu.max():.2e}; "
+              f"V median {np.median(ev):.2e} max {ev.max():.2e}", flush=True)
+        assert np.median(eu) <= med and eu.max() <= mx, shape
+        assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx, shape
+        assert s.info()["fallback_rows"] == 0
+        del s
+
+
+def test_autotune_returns_a_timed_candidate():
+    from paper_1705_10633_amd import autotune
+    from paper_1705_10633_amd.sampler import DeviceRatings
+    prob = _skewed(32, seed=5)
+    cands = autotune.candidate_shapes([prob.R.row_counts(), prob.R.col_counts()], prob.K)
+    assert len(cands) > 4
+    R = DeviceRatings(prob.R, val_dtype="float32")
+    best, table = autotune.tune(R, prob.K, prob.U0.astype(np.float32), prob.V0.astype(np.float32),
+                                [prob.R.row_counts(), prob.R.col_counts()], precision="bf16",
+                                sweeps=3, warmup=1, mean_rating=prob.mean_rating)
+    assert [c for c, _ in table] == cands
+    assert all(ms > 0 for _, ms in table)
+    assert best in cands
+    assert min(ms for _, ms in table) == next(ms for c, ms in table if c == best)
