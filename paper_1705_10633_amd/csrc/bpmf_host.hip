@@ -105,7 +105,8 @@ static LaunchShape resolve_shape(const bpmf_launch_shape *sh, int K)
     if (!sh) return r;
     if (sh->heavy_min_ratings) r.heavy_min = sh->heavy_min_ratings;
     if (sh->piece_min_ratings) r.piece_min = sh->piece_min_ratings;
-    if (sh->rank1_max_ratings) r.rank1_max = sh->rank1_max_ratings < 0 ? 0 : sh->rank1_max_ratings;
+    // -1: no row qualifies, not even rows without ratings
+    if (sh->rank1_max_ratings) r.rank1_max = sh->rank1_max_ratings < 0 ? -1 : sh->rank1_max_ratings;
     r.heavy_split = sh->heavy_split;
     r.rank1_split = sh->rank1_split;
     return r;

@@ -75,3 +75,39 @@ def test_autotune_returns_a_timed_candidate():
     assert all(ms > 0 for _, ms in table)
     assert best in cands
     assert min(ms for _, ms in table) == next(ms for c, ms in table if c == best)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_side_entirely_in_the_rank_one_launch(precision):
+    """Every user has at most two ratings and the shape forces the rank-one
+    launch, so the users' one-wavefront launch is empty; with the rank-one
+    kernels switched off the same rows, those without ratings included, run
+    in the full kernel.  Both meet the oracle."""
+    K = 32
+    rng = np.random.default_rng(3)
+    M, N = 700, 400
+    counts = rng.integers(0, 3, M)
+    rows = np.repeat(np.arange(M), counts)
+    cols = np.concatenate([rng.choice(N, c, replace=False) for c in counts]).astype(np.int64)
+    vals = 3.0 + rng.standard_normal(rows.size)
+    R = synth.from_coo(M, N, rows, cols, vals)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    prob = synth.Problem("all-small", R, K, 2.0, np.zeros(K), 2.0, float(K), np.eye(K), 1, 0,
+                         f32(0.3 * rng.standard_normal((M, K))), f32(0.3 * rng.standard_normal((N, K))),
+                         np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), 0, float(vals.mean()))
+    tape = tape_for(prob, 1, seed=9)
+    ref = O.gibbs(prob, tape, n_sweeps=1, nthreads=8)
+    med, mx = MIXED_TOL[precision]
+    import torch
+    for shape in ({"rank1_max_ratings": 2, "rank1_split": 1}, {"rank1_max_ratings": -1}):
+        s = make_sampler(prob, precision=precision, with_test=False, shape=shape)
+        s.sweep(1, tape=_dev(tape))
+        torch.cuda.synchronize()
+        eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+        ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+        print(f"{precision} {shape}: U median {np.median(eu):.2e} max {eu.max():.2e}; "
+              f"V median {np.median(ev):.2e} max {ev.max():.2e}", flush=True)
+        assert np.median(eu) <= med and eu.max() <= mx, shape
+        assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx, shape
+        assert s.info()["fallback_rows"] == 0
+        del s
