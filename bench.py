@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--autotune", action="store_true",
                     help="time every candidate launch shape first and sweep with the fastest")
+    ap.add_argument("--shape", default=None,
+                    help="launch shape to sweep with, as JSON (bpmf_launch_shape fields)")
     ap.add_argument("--only-timed", action="store_true",
                     help="run only warm-up and timed sweeps (for profiler runs)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -211,6 +213,10 @@ def main():
         log("bench.py: the sampler and its kernels run on one GPU; multi-GPU sharding is not built")
         sys.exit(2)
 
+    if args.autotune and args.shape:
+        log("bench.py: --autotune and --shape exclude each other")
+        sys.exit(2)
+
     import torch
     from paper_1705_10633_amd import synth
     from paper_1705_10633_amd.sampler import DeviceRatings, Sampler
@@ -224,7 +230,7 @@ def main():
         f"nnz={prob.R.nnz} K={K} ({prob.note})")
 
     R32 = DeviceRatings(prob.R, val_dtype="float32")
-    shape, tune_table = {}, None
+    shape, tune_table = (json.loads(args.shape) if args.shape else {}), None
     if args.autotune:
         from paper_1705_10633_amd import autotune
         t0 = time.perf_counter()
