@@ -175,3 +175,16 @@ def test_autotune_candidates_follow_the_counts():
     assert not any(c.get("rank1_max_ratings") == 4 for c in mixed)   # no row has 4 ratings
     assert all(c.get("heavy_min_ratings", 0) <= 9000 for c in mixed)
     assert candidate_shapes([np.array([1, 9000])], 100) == [{}]     # K > 64: one launch shape
+
+
+def test_autotune_result_round_trips(tmp_path):
+    """A stored tuning result is returned only for the problem key it was
+    tuned on."""
+    from paper_1705_10633_amd import autotune
+    key = {"M": 10, "N": 8, "nnz": 20, "K": 32, "precision": "fp32"}
+    shape = {"heavy_split": 1, "heavy_min_ratings": 1024, "piece_min_ratings": 1024}
+    path = str(tmp_path / "shape.json")
+    autotune.save(path, shape, [({}, 0.36), (shape, 0.30)], key)
+    assert autotune.load(path, key) == shape
+    assert autotune.load(path, {**key, "K": 64}) is None
+    assert autotune.load(str(tmp_path / "missing.json"), key) is None
