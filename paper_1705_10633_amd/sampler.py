@@ -57,9 +57,22 @@ class Sampler:
                  alpha: float = 2.0, beta0: float = 2.0, nu0: Optional[float] = None,
                  mu0=None, W0=None, mean_rating: float = float("nan"), seed: int = 0,
                  burnin: int = 0, test_rows=None, test_cols=None, use_graph: bool = False,
-                 validate: bool = False, stream=None, shape: Optional[dict] = None):
+                 validate: bool = False, stream=None, shape=None):
         torch = _torch()
         self.torch = torch
+        self.tune_table = None
+        if isinstance(shape, str):
+            # "auto": time the candidate launch shapes on this problem first and keep the
+            # fastest (only the mixed-precision kernels for K <= 64 have shapes to choose)
+            if shape != "auto":
+                raise ValueError("shape must be None, a dict of bpmf_launch_shape fields or 'auto'")
+            shape = {}
+            if precision != "fp64" and K <= 64:
+                from . import autotune
+                counts = [torch.diff(ratings.row_ptr).cpu().numpy(), torch.diff(ratings.col_ptr).cpu().numpy()]
+                shape, self.tune_table = autotune.tune(
+                    ratings, K, U0, V0, counts, precision=precision, alpha=alpha, beta0=beta0, nu0=nu0,
+                    mu0=mu0, W0=W0, mean_rating=mean_rating, seed=seed)
         self.R = ratings
         self.K = K
         self.precision = precision

@@ -111,3 +111,31 @@ def test_side_entirely_in_the_rank_one_launch(precision):
         assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx, shape
         assert s.info()["fallback_rows"] == 0
         del s
+
+
+def test_sampler_with_automatic_shape_meets_the_oracle():
+    """shape="auto" tunes on the sampler's own problem, keeps one of the
+    timed candidates, and the sampler it builds meets the oracle."""
+    from paper_1705_10633_amd import autotune
+    K, precision = 32, "fp32"
+    prob = _f32_start(_skewed(K, seed=21))
+    tape = tape_for(prob, 1, seed=22)
+    ref = O.gibbs(prob, tape, n_sweeps=1, nthreads=8)
+    import torch
+    from paper_1705_10633_amd.sampler import DeviceRatings, Sampler
+    s = Sampler(DeviceRatings(prob.R, val_dtype="float32"), K, prob.U0.astype(np.float32),
+                prob.V0.astype(np.float32), precision=precision, alpha=prob.alpha, beta0=prob.beta0,
+                nu0=prob.nu0, mean_rating=prob.mean_rating, shape="auto")
+    cands = autotune.candidate_shapes([prob.R.row_counts(), prob.R.col_counts()], K)
+    assert [c for c, _ in s.tune_table] == cands and s.shape in cands
+    print(f"kept {s.shape}", flush=True)
+    s.sweep(1, tape=_dev(tape))
+    torch.cuda.synchronize()
+    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    med, mx = MIXED_TOL[precision]
+    assert np.median(eu) <= med and eu.max() <= mx
+    assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx
+    with pytest.raises(ValueError):
+        Sampler(DeviceRatings(prob.R, val_dtype="float32"), K, prob.U0.astype(np.float32),
+                prob.V0.astype(np.float32), precision=precision, shape="fastest")
