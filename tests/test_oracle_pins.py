@@ -314,6 +314,32 @@ def test_philox_block_layout():
     assert np.all(blk[:K] > 0)
 
 
+@pytest.mark.parametrize("K,n_rows,nu0", [(5, 0, 5.3), (3, 1, 2.1)])
+def test_philox_block_chi_square_entries(K, n_rows, nu0):
+    """The first K entries of a block are the Bartlett diagonal's chi-square
+    draws with nu* - k degrees of freedom, nu* = nu0 + n_rows (k = 0..K-1):
+    over 10^4 blocks (distinct half-sweep indices) each entry's mean is
+    nu* - k and its variance 2 (nu* - k) within 5 standard errors, and the
+    first and last entries pass a Kolmogorov-Smirnov test against chi^2.
+    The degrees of freedom are small and differ by one between entries, so a
+    dropped factor 2, a shift of k by one or a missing n_rows fails; the last
+    entry's shape (nu* - K + 1)/2 < 1 takes the shape-boost branch."""
+    n = 10000
+    X = np.stack([O.philox_block(seed=77, h=h, n_rows=n_rows, K=K, nu0=nu0)[:K] for h in range(n)])
+    nus = nu0 + n_rows
+    assert (nus - (K - 1)) / 2 < 1.0
+    for k in range(K):
+        dof = nus - k
+        m, v = X[:, k].mean(), X[:, k].var()
+        assert abs(m - dof) < 5 * math.sqrt(2 * dof / n), (k, m, dof)
+        # variance of the sample variance of chi^2(d): (2 mu4 - ... ) ~ (8 d^2 + 48 d) / n
+        assert abs(v - 2 * dof) < 5 * math.sqrt((8 * dof ** 2 + 48 * dof) / n), (k, v, dof)
+    for k in (0, K - 1):
+        assert scipy.stats.kstest(X[:, k], scipy.stats.chi2(nus - k).cdf).pvalue > 1e-4
+    # independent across entries of a block
+    assert abs(np.corrcoef(X[:, 0], X[:, 1])[0, 1]) < 5 / math.sqrt(n)
+
+
 def test_tape_lengths_agree():
     for M, N, K in [(10, 7, 3), (1000, 500, 10)]:
         t = synth.make_tape(np.random.default_rng(0), 2, M, N, K, float(K))
