@@ -173,7 +173,8 @@ bpmf_status bpmf_init(bpmf_ctx **ctx, const bpmf_ratings *R, const bpmf_params *
 bpmf_status bpmf_sweep(bpmf_ctx *ctx, int32_t n_sweeps, const double *d_tape, int64_t tape_len,
                        void *stream);
 
-/* Predictions u_i . v_j + rbar of the current sample for n pairs (device
+/* Algorithm 1's prediction step for arbitrary pairs: predictions
+ * u_i . v_j + rbar of the current sample for n pairs (device
  * int32 rows/cols, device double output).  Errors: BPMF_E_INVALID if n < 0 or
  * pointers are NULL with n > 0 (indices are range-checked only when
  * validate = 1, on the host). */
@@ -200,9 +201,13 @@ typedef struct {
 /* Counters; synchronises `stream`. */
 bpmf_status bpmf_get_info(bpmf_ctx *ctx, bpmf_info *info, void *stream);
 
-/* Copies the current movie factors (as float, N x K) and the user-side
- * hyper-parameters (Lambda_U as double K x K, mu_U as double K) into a
- * caller-owned fold-in sample slot (device pointers). */
+/* Serving support (not a step of the paper's sampler): keeps a posterior
+ * sample for folding in new users.  Copies the current movie factors (as
+ * float, N x K) and the user-side hyper-parameters (Lambda_U as double
+ * K x K, mu_U as double K) into a caller-owned fold-in sample slot (device
+ * pointers); S such slots, taken a sweep or more apart, form the
+ * bpmf_foldin_model of the fold-in functions below.  Errors: BPMF_E_STATE,
+ * BPMF_E_INVALID (NULL slot), BPMF_E_HIP. */
 bpmf_status bpmf_snapshot(bpmf_ctx *ctx, float *d_V_slot, double *d_Lambda_slot,
                           double *d_mu_slot, void *stream);
 
@@ -255,7 +260,9 @@ typedef struct {
 bpmf_status bpmf_foldin_workspace_size(const bpmf_foldin_model *m, int64_t n_queries,
                                        size_t *bytes);
 
-/* For each request r (ratings d_cols/d_vals[d_req_ptr[r] .. d_req_ptr[r+1]),
+/* Fold-in of new users (serving; the paper's row conditional of Section 2
+ * with z = 0, averaged over stored posterior samples, not a step of its
+ * sampler).  For each request r (ratings d_cols/d_vals[d_req_ptr[r] .. d_req_ptr[r+1]),
  * query columns d_q_cols[d_q_ptr[r] .. d_q_ptr[r+1]), d_q_ptr[n_req] =
  * n_queries) and each sample s:
  *   m_s = (Lambda_s + alpha sum_j v_j v_j^T)^{-1}(Lambda_s mu_s + alpha sum_j (r_j - rbar) v_j)
@@ -263,8 +270,11 @@ bpmf_status bpmf_foldin_workspace_size(const bpmf_foldin_model *m, int64_t n_que
  * arithmetic, samples summed in order).  Stateless: calls on different
  * streams with different workspaces may overlap.  Each request's result does
  * not depend on the other requests in the batch.  Errors: BPMF_E_INVALID,
- * BPMF_E_WORKSPACE, BPMF_E_HIP.  K must be <= 64.  A sample whose FP32
- * Cholesky pivot fails yields NaN predictions for that request. */
+ * BPMF_E_WORKSPACE, BPMF_E_HIP.  K must be <= 64.  A (request, sample) pair
+ * whose FP32 Cholesky pivot is not finite or not above 64 K 2^-24 max_k P_kk
+ * is recomputed in FP64 (Gram of the FP32 sample rows, Cholesky and solves in
+ * FP64) before the average over samples; only a pivot that fails in FP64 too
+ * (a model that is not SPD) gives NaN predictions. */
 bpmf_status bpmf_foldin(const bpmf_foldin_model *m, int64_t n_req, const int64_t *d_req_ptr,
                         const int32_t *d_cols, const float *d_vals, const int64_t *d_q_ptr,
                         const int32_t *d_q_cols, int64_t n_queries, float *d_out, void *d_ws,
@@ -309,7 +319,10 @@ bpmf_status bpmf_server_create(bpmf_server **srv, const bpmf_foldin_model *m,
  * host memory; the dispatcher writes a queued request into a free slot, the
  * kernel computes it (one workgroup per slot, one wavefront in it per stored
  * sample, the same arithmetic as bpmf_foldin, so the same predictions) and
- * writes the predictions back.  A request's samples share one compute unit,
+ * writes the predictions back.  The resident kernel has no FP64 path: a
+ * request with a (request, sample) pair whose FP32 pivot fails is computed
+ * again by bpmf_foldin on a stream of the server, which recomputes that pair
+ * in FP64, so predictions equal batching mode's in that case too.  A request's samples share one compute unit,
  * so large requests take longer than in batching mode, which spreads them.
  * The kernel ends after idle_polls polls without a request (0: 500000, about
  * a second) or when the server is destroyed, and is launched again when a

@@ -984,15 +984,22 @@ bpmf_status bpmf_foldin_workspace_size(const bpmf_foldin_model *m, int64_t n_que
     return BPMF_OK;
 }
 
-bpmf_status bpmf_foldin(const bpmf_foldin_model *m, int64_t n_req, const int64_t *d_req_ptr,
-                        const int32_t *d_cols, const float *d_vals, const int64_t *d_q_ptr,
-                        const int32_t *d_q_cols, int64_t n_queries, float *d_out, void *d_ws,
-                        size_t ws_bytes, void *stream)
+static bpmf_status check_foldin_model(const bpmf_foldin_model *m)
 {
     if (!m) return fail(BPMF_E_INVALID, "NULL model");
     if (m->S < 1 || m->K < 1 || m->K > 64 || m->N < 1) return fail(BPMF_E_INVALID, "fold-in needs S >= 1, 1 <= K <= 64, N >= 1");
     if (!m->d_V || !m->d_Lambda || !m->d_mu) return fail(BPMF_E_INVALID, "NULL model arrays");
     if (!(m->alpha > 0.0)) return fail(BPMF_E_INVALID, "alpha must be > 0");
+    return BPMF_OK;
+}
+
+bpmf_status bpmf_foldin(const bpmf_foldin_model *m, int64_t n_req, const int64_t *d_req_ptr,
+                        const int32_t *d_cols, const float *d_vals, const int64_t *d_q_ptr,
+                        const int32_t *d_q_cols, int64_t n_queries, float *d_out, void *d_ws,
+                        size_t ws_bytes, void *stream)
+{
+    bpmf_status st = check_foldin_model(m);
+    if (st != BPMF_OK) return st;
     if (n_req < 0 || n_queries < 0) return fail(BPMF_E_INVALID, "negative sizes");
     if (n_req == 0) return BPMF_OK;
     if (!d_req_ptr || !d_q_ptr || (n_queries > 0 && (!d_q_cols || !d_out)))

@@ -70,11 +70,21 @@ __device__ __forceinline__ void box_muller_f64(u32x4 w, double &z0, double &z1)
     z1 = rad * s;
 }
 
+// -log(u) for the 53-bit uniform u of (hi, lo), to a few FP32 ulps over all
+// of (0, 1).  Rounding u itself to FP32 would cost up to 2^-25 / (1 - u) of
+// relative accuracy near u = 1; there the exact complement 1 - u (the
+// uniform of the inverted 53 bits) is rounded instead and log1p is taken.
+__device__ __forceinline__ float neglog_uniform53_f32(uint32_t hi, uint32_t lo)
+{
+    const float u = uniform53_f32(hi, lo);
+    const float v = uniform53_f32(~hi, ~lo);
+    return u < 0.5f ? -logf(u) : -log1pf(-v);
+}
+
 __device__ __forceinline__ void box_muller_f32(u32x4 w, float &z0, float &z1)
 {
-    float u1 = uniform53_f32(w.x, w.y);
     float u2 = uniform53_f32(w.z, w.w);
-    float rad = sqrtf(-2.0f * logf(u1));
+    float rad = sqrtf(2.0f * neglog_uniform53_f32(w.x, w.y));
     float s, c;
     sincospif(2.0f * u2, &s, &c);
     z0 = rad * c;

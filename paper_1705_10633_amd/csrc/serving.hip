@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -102,6 +103,7 @@ struct bpmf_server {
     int32_t *r_stop = nullptr;        // coherent pinned host memory
     char *r_dev = nullptr;            // device staging
     hipStream_t r_stream = nullptr;
+    hipStream_t r_fb_stream = nullptr;  // FP64 recompute of requests whose FP32 pivot failed
     std::vector<Req> r_req;
     std::vector<int32_t> r_seq;
     std::vector<char> r_busy;
@@ -246,16 +248,56 @@ static void worker_loop(bpmf_server *srv)
 }
 
 // Device staging of the resident server: cols and vals (max_nnz per slot),
-// query columns (max_q per slot), then Lambda_s mu_s (S x K).
+// query columns (max_q per slot), Lambda_s mu_s (S x K), then one batch of
+// bpmf_foldin for a single request of at most max_nnz ratings and max_q
+// queries (the FP64 recompute of a request whose FP32 pivot failed).
 static size_t resident_dev_bytes(int32_t n_slots, int32_t max_nnz, int32_t max_q, int S, int K)
 {
-    return 2 * al(4 * (size_t)n_slots * max_nnz) + al(4 * (size_t)n_slots * max_q) + al(4 * (size_t)S * K);
+    return 2 * al(4 * (size_t)n_slots * max_nnz) + al(4 * (size_t)n_slots * max_q) + al(4 * (size_t)S * K) +
+           batch_bytes(1, max_nnz, max_q, S);
 }
 
 static float *resident_lam_mu(bpmf_server *srv)
 {
     return (float *)(srv->r_dev + 2 * al(4 * (size_t)srv->n_slots * srv->max_nnz) +
                      al(4 * (size_t)srv->n_slots * srv->max_q));
+}
+
+static char *resident_fallback_buf(bpmf_server *srv)
+{
+    return (char *)resident_lam_mu(srv) + al(4 * (size_t)srv->m.S * srv->m.K);
+}
+
+// The resident kernel has no FP64 path: a (request, sample) pair whose FP32
+// pivot fails comes back as NaN predictions.  Such a request is computed
+// again by bpmf_foldin, which takes the pairs that pass in FP32 with the same
+// arithmetic as the resident kernel and recomputes the failed ones in FP64,
+// so its predictions are those of batching mode.  Rare: the dispatcher waits
+// for it on a stream of its own.
+static bool resident_recompute(bpmf_server *srv, const Req &r, std::vector<float> &preds)
+{
+    const int64_t nnz = (int64_t)r.cols.size(), nq = (int64_t)r.qcols.size();
+    char *d = resident_fallback_buf(srv);
+    const size_t o_rp = 0, o_qp = o_rp + al(16), o_c = o_qp + al(16), o_qc = o_c + al(4 * nnz),
+                 o_v = o_qc + al(4 * nq), o_out = o_v + al(4 * nnz), o_ws = o_out + al(4 * nq);
+    const int64_t rp[2] = {0, nnz}, qp[2] = {0, nq};
+    hipStream_t st = srv->r_fb_stream;
+    if (hipMemcpyAsync(d + o_rp, rp, 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d + o_qp, qp, 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+        (nnz > 0 && hipMemcpyAsync(d + o_c, r.cols.data(), 4 * nnz, hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (nnz > 0 && hipMemcpyAsync(d + o_v, r.vals.data(), 4 * nnz, hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipMemcpyAsync(d + o_qc, r.qcols.data(), 4 * nq, hipMemcpyHostToDevice, st) != hipSuccess)
+        return false;
+    if (bpmf_foldin(&srv->m, 1, (const int64_t *)(d + o_rp), (const int32_t *)(d + o_c), (const float *)(d + o_v),
+                    (const int64_t *)(d + o_qp), (const int32_t *)(d + o_qc), nq, (float *)(d + o_out), d + o_ws,
+                    al(4 * (size_t)srv->m.S * std::max<int64_t>(nq, 1)), st) != BPMF_OK)
+        return false;
+    std::vector<float> out(nq);
+    if (hipMemcpyAsync(out.data(), d + o_out, 4 * nq, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return false;
+    preds.swap(out);
+    return true;
 }
 
 static bpmf::ResidentArgs resident_args(bpmf_server *srv)
@@ -307,6 +349,9 @@ static void resident_loop(bpmf_server *srv)
             Done dn;
             dn.id = r.id;
             dn.preds.assign(out, out + r.qcols.size());
+            bool nan_seen = false;
+            for (float v : dn.preds) nan_seen |= std::isnan(v);
+            if (nan_seen) resident_recompute(srv, r, dn.preds);
             dn.latency = std::chrono::duration<double>(t - r.t_submit).count();
             std::lock_guard<std::mutex> lk(srv->mu);
             srv->done.push_back(std::move(dn));
@@ -405,6 +450,7 @@ bpmf_status bpmf_server_create_resident(bpmf_server **out, const bpmf_foldin_mod
     const size_t dev_bytes = resident_dev_bytes(n_slots, max_nnz, max_q, m->S, m->K);
     if (hipGetDevice(&srv->device) != hipSuccess ||
         hipStreamCreateWithFlags(&srv->r_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&srv->r_fb_stream, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void **)&srv->r_slots, srv->r_slot_bytes * n_slots, hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc((void **)&srv->r_stop, kAlign, hipHostMallocCoherent) != hipSuccess ||
         hipMalloc((void **)&srv->r_dev, dev_bytes) != hipSuccess ||
@@ -602,6 +648,10 @@ bpmf_status bpmf_server_destroy(bpmf_server *srv)
     srv->cv_submit.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
     if (srv->r_stop) __atomic_store_n(srv->r_stop, 1, __ATOMIC_RELEASE);
+    if (srv->r_fb_stream) {
+        hipStreamSynchronize(srv->r_fb_stream);
+        hipStreamDestroy(srv->r_fb_stream);
+    }
     if (srv->r_stream) {
         hipStreamSynchronize(srv->r_stream);
         hipStreamDestroy(srv->r_stream);

@@ -15,7 +15,8 @@ import pytest
 from oracle import oracle as O
 from paper_1705_10633_amd import synth
 
-from .gpu_common import make_sampler, row_rel_err, tape_for
+from .gpu_common import (ARITH_TOL, MIXED_FLOOR, MIXED_TOL, bf16_round, check_arith, make_sampler, row_rel_err,
+                         row_rel_err_fp64, tape_for, within)
 
 pytestmark = pytest.mark.gpu
 
@@ -52,8 +53,8 @@ def test_fp64_tape_parity_uniform_planted(n_sweeps):
     tape = tape_for(prob, n_sweeps)
     ref = O.gibbs(prob, tape, nthreads=8, want_hyper=True)
     s = _run_gpu(prob, tape, n_sweeps)
-    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
-    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    eu = row_rel_err_fp64(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err_fp64(s.V.cpu().numpy(), ref["V"])
     print(f"sweeps={n_sweeps} max row err U {eu.max():.3e} V {ev.max():.3e}")
     assert eu.max() <= FP64_TOL and ev.max() <= FP64_TOL
     h = s.hyper()
@@ -75,8 +76,8 @@ def test_fp64_device_generator_parity():
     tape = O.philox_tape(seed, 0, 3, prob.M, prob.N, prob.K, prob.nu0)
     ref = O.gibbs(prob, tape, nthreads=8, want_hyper=True)
     s = _run_gpu(prob, None, 3, seed=seed)
-    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
-    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    eu = row_rel_err_fp64(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err_fp64(s.V.cpu().numpy(), ref["V"])
     print(f"philox max row err U {eu.max():.3e} V {ev.max():.3e}")
     assert eu.max() <= FP64_TOL and ev.max() <= FP64_TOL
     # the users' hyper step runs one sweep ahead with device draws; the
@@ -97,8 +98,8 @@ def test_fp64_shapes_and_empty_rows(K, M, N, nnz):
     tape = tape_for(prob, 2, seed=K)
     ref = O.gibbs(prob, tape, nthreads=8)
     s = _run_gpu(prob, tape, 2)
-    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
-    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    eu = row_rel_err_fp64(s.U.cpu().numpy(), ref["U"])
+    ev = row_rel_err_fp64(s.V.cpu().numpy(), ref["V"])
     print(f"K={K} max row err U {eu.max():.3e} V {ev.max():.3e}")
     assert eu.max() <= FP64_TOL and ev.max() <= FP64_TOL
 
@@ -118,30 +119,47 @@ def _one_sweep_from_f32_state(prob, precision, tape):
     return s, ref
 
 
-# Tolerances for one mixed sweep (median, max of the per-row relative error of
-# the users' half; the movies' half also carries the users' error).
-#  FP32: Gram, Cholesky and solves in FP32 with inputs exact in FP32: unit
-#        roundoff 6e-8 times K-sized sums and cond(P) (< ~1e3 here) -> 1e-5 / 1e-3.
-#  BF16: gathered rows rounded to 8 bits (relative 2^-9 = 2e-3); the Gram and
-#        rhs errors are amplified by cond(P) -> median 1e-2, max 1e-1.
-MIXED_TOL = {"fp32": (1e-5, 1e-3), "bf16": (1e-2, 1e-1)}
+# One mixed sweep is compared twice: with the plain FP64 oracle (the whole
+# mixed-precision error, MIXED_TOL; the movies' half also carries the users'
+# error, so it gets three times the bound) and, through check_arith, with the
+# oracle fed the inputs as the kernels round them (the FP32 arithmetic alone,
+# ARITH_TOL).  Both are defined and derived in gpu_common.
 
 
-@pytest.mark.parametrize("precision,K", [(p, k) for p in ("fp32", "bf16") for k in (10, 32, 64)]
-                         + [("bf16", 100), ("bf16", 128), ("fp32", 100)])
+def _mixed_errors(s, ref):
+    return (row_rel_err(s.U.cpu().numpy(), ref["U"], MIXED_FLOOR),
+            row_rel_err(s.V.cpu().numpy(), ref["V"], MIXED_FLOOR))
+
+
+def _assert_mixed(prob, eu, ev, precision, rows=None):
+    cu, cv = prob.R.row_counts(), prob.R.col_counts()
+    if rows is not None:
+        cu = cu[rows]
+    assert within(eu, cu, MIXED_TOL[precision])
+    assert within(ev, cv, MIXED_TOL[precision], factor=3.0)
+
+
+MIXED_CASES = ([(p, k) for p in ("fp32", "bf16") for k in (1, 10, 31, 32, 33, 63, 64)]
+               + [("bf16", k) for k in (65, 100, 127, 128)] + [("fp32", 65), ("fp32", 100)])
+
+
+@pytest.mark.parametrize("precision,K", MIXED_CASES)
 def test_mixed_one_sweep_error(precision, K):
-    """K <= 64: one wavefront per row; BF16 with 64 < K <= 128: the blocked
-    four-wavefront kernel; FP32 with K > 64: FP64 row arithmetic."""
-    prob = synth.uniform_planted(M=600, N=300, K=K, nnz=30000, seed=K, n_sweeps=1, burnin=0)
+    """K <= 64: one wavefront per row (K = 1, 31, 33, 63 pad the identity
+    block of the 32 / 64 kernels); BF16 with 64 < K <= 128: the blocked
+    four-wavefront kernel (65 and 127 pad to 128); FP32 with K > 64: FP64 row
+    arithmetic on FP32 storage.  Two users and two movies have no ratings."""
+    M, N = 600, 300
+    prob = with_empty(synth.uniform_planted(M=M, N=N, K=K, nnz=30000, seed=K, n_sweeps=1, burnin=0),
+                      rows=[0, M // 2], cols=[1, N - 1])
     tape = tape_for(prob, 1, seed=K + 1)
     s, ref = _one_sweep_from_f32_state(prob, precision, tape)
-    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
-    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
-    med, mx = MIXED_TOL[precision]
+    eu, ev = _mixed_errors(s, ref)
     print(f"{precision} K={K}: U median {np.median(eu):.2e} p99 {np.quantile(eu, .99):.2e} max {eu.max():.2e}; "
           f"V median {np.median(ev):.2e} max {ev.max():.2e}; fallback {s.info()['fallback_rows']}")
-    assert np.median(eu) <= med and eu.max() <= mx
-    assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx
+    _assert_mixed(prob, eu, ev, precision)
+    assert s.info()["fallback_rows"] == 0
+    check_arith(_f32_start(prob), s, tape, precision, "one sweep")
 
 
 def _few_ratings(K, seed):
@@ -167,17 +185,19 @@ def test_rank_one_rows_one_sweep_error(precision, K):
     prob = _few_ratings(K, seed=K + 7)
     tape = tape_for(prob, 1, seed=K + 3)
     s, ref = _one_sweep_from_f32_state(prob, precision, tape)
-    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
-    ev = row_rel_err(s.V.cpu().numpy(), ref["V"])
+    eu, ev = _mixed_errors(s, ref)
     small = prob.R.row_counts() <= (3 if K <= 32 else 2)
     assert small.sum() > 400 and (~small).sum() >= 40
-    med, mx = MIXED_TOL[precision]
-    for name, e in (("rank-one", eu[small]), ("full", eu[~small])):
+    for name, sel in (("rank-one", small), ("full", ~small)):
+        e = eu[sel]
         print(f"{precision} K={K} {name} users ({e.size}): median {np.median(e):.2e} max {e.max():.2e}")
-        assert np.median(e) <= med and e.max() <= mx
+        assert within(e, prob.R.row_counts()[sel], MIXED_TOL[precision])
     print(f"  movies: median {np.median(ev):.2e} max {ev.max():.2e}")
-    assert np.median(ev) <= 3 * med and ev.max() <= 3 * mx
+    assert within(ev, prob.R.col_counts(), MIXED_TOL[precision], factor=3.0)
     assert s.info()["fallback_rows"] == 0
+    p32 = _f32_start(prob)
+    check_arith(p32, s, tape, precision, "rank-one rows", rows=small)
+    check_arith(p32, s, tape, precision, "full-kernel rows", rows=~small)
 
 
 def _heavy_rows(K, seed):
@@ -198,50 +218,100 @@ def _heavy_rows(K, seed):
 
 @pytest.mark.parametrize("precision,K", [(p, k) for p in ("fp32", "bf16") for k in (20, 64)])
 def test_heavy_rows_one_sweep_error(precision, K):
-    """Rows with at least 2048 ratings split their gathers and Gram over eight
-    wavefronts and sum the partial tiles in a fixed tree; they meet the bounds
-    of the one-wavefront rows, and two runs give identical bits."""
+    """Rows with at least 2048 ratings are cut into pieces that run as their
+    own entries of the one-wavefront launch; a second launch sums each row's
+    piece tiles in piece order and factors the row.  They meet the bounds of
+    the other rows, and two runs give identical bits."""
     prob = _heavy_rows(K, seed=K)
     tape = tape_for(prob, 1, seed=K + 5)
     s, ref = _one_sweep_from_f32_state(prob, precision, tape)
-    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
+    eu, _ = _mixed_errors(s, ref)
     heavy = prob.R.row_counts() >= 2048
     assert heavy.sum() == 8
-    med, mx = MIXED_TOL[precision]
-    for name, e in (("heavy", eu[heavy]), ("other", eu[~heavy])):
+    for name, sel in (("heavy", heavy), ("other", ~heavy)):
+        e = eu[sel]
         print(f"{precision} K={K} {name} users ({e.size}): median {np.median(e):.2e} max {e.max():.2e}")
-        assert np.median(e) <= med and e.max() <= mx
-    again = _run_gpu(_f32_start(prob), tape, 1, precision=precision)
+        assert within(e, prob.R.row_counts()[sel], MIXED_TOL[precision])
+    p32 = _f32_start(prob)
+    check_arith(p32, s, tape, precision, "heavy rows", rows=heavy)
+    check_arith(p32, s, tape, precision, "other rows", rows=~heavy)
+    again = _run_gpu(p32, tape, 1, precision=precision)
     import torch
     assert torch.equal(again.U, s.U) and torch.equal(again.V, s.V)
 
 
-def test_fp32_pivot_failure_falls_back_to_fp64():
-    """With one rating per user and alpha = 1e9, P = Lambda + alpha v v^T has a
-    largest diagonal ~ alpha |v|^2 ~ 1e7 while the pivots after the first are
-    ~ Lambda_kk ~ 1e2, below 64 K 2^-24 max P_kk ~ 6e2: every user row is
-    flagged (the identity padding of K = 16 up to 32 is not), recomputed in
-    FP64 from the FP32 factors, and agrees with the FP64 oracle."""
-    M, N, K = 200, 150, 16
-    rng = np.random.default_rng(5)
-    rows = np.arange(M)
-    cols = rng.integers(0, N, M)
-    vals = rng.standard_normal(M)
+def _pivot_failure_problem(K, n_user_ratings, M=600, N=None, seed=5):
+    """alpha = 1e9 and n_user_ratings < K ratings per user: P = Lambda +
+    alpha sum v v^T has its largest diagonal ~ alpha |v|^2 ~ 1e7 while the
+    pivots past the rated directions are ~ Lambda_kk ~ 1e2, below
+    64 K 2^-24 max P_kk (~ 1e3): every user row is flagged (the identity
+    padding up to 32 / 64 / 128 is not), recomputed in FP64 from the FP32
+    factors.  With K <= 32 each of the N = 20 movies has ~ 60 raters, so the
+    movies' rows have full rank and stay in the FP32 kernels, which in BF16
+    mode gather the BF16 copy of U that the recompute rewrote; with K > 32
+    (N = 40) every movie has fewer raters than K and is recomputed too."""
+    rng = np.random.default_rng(seed)
+    N = N or (20 if K <= 32 else 40)
+    rows = np.repeat(np.arange(M), n_user_ratings)
+    cols = np.concatenate([rng.choice(N, n_user_ratings, replace=False) for _ in range(M)]).astype(np.int64)
+    vals = rng.standard_normal(rows.size)
     R = synth.from_coo(M, N, rows, cols, vals)
-    prob = synth.Problem("single", R, K, 1e9, np.zeros(K), 2.0, float(K), np.eye(K), 1, 0,
+    return synth.Problem("pivot", R, K, 1e9, np.zeros(K), 2.0, float(K), np.eye(K), 1, 0,
                          (0.1 * rng.standard_normal((M, K))).astype(np.float32).astype(np.float64),
                          (0.1 * rng.standard_normal((N, K))).astype(np.float32).astype(np.float64),
                          np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), 0, 0.0)
+
+
+PIVOT_CASES = [
+    # (precision, K, ratings per user, launch shape): which kernel meets the failing pivot
+    ("fp32", 16, 1, None),                                         # one lane per row
+    ("fp32", 16, 2, {"rank1_max_ratings": 3, "rank1_split": 1}),  # rank-one updates
+    ("fp32", 16, 2, {"rank1_max_ratings": -1}),                    # one wavefront per row
+    ("bf16", 16, 2, {"rank1_max_ratings": 3, "rank1_split": 1}),
+    ("bf16", 16, 2, {"rank1_max_ratings": -1}),
+    ("bf16", 32, 3, {"rank1_max_ratings": -1}),
+    ("fp32", 64, 2, {"rank1_max_ratings": -1}),
+    ("bf16", 100, 2, None),                                        # four wavefronts per row
+]
+
+
+@pytest.mark.parametrize("precision,K,nr,shape", PIVOT_CASES)
+def test_fp32_pivot_failure_falls_back_to_fp64(precision, K, nr, shape):
+    """Rows whose FP32 pivot fails are recomputed in FP64 arithmetic from the
+    FP32 factors; U agrees with the FP64 oracle, and V with the oracle's
+    movies' half-sweep fed the GPU's U (the FP64 recompute gathers FP32
+    masters, the FP32 kernels the BF16 copy in BF16 mode)."""
+    prob = _pivot_failure_problem(K, nr)
     tape = tape_for(prob, 1, seed=3)
-    ref = O.gibbs(prob, tape, n_sweeps=1, nthreads=8)
-    s = make_sampler(prob, precision="fp32", with_test=False)
+    ref = O.gibbs(prob, tape, n_sweeps=1, nthreads=8, want_hyper=True)
+    s = make_sampler(prob, precision=precision, with_test=False, shape=shape)
     s.sweep(1, tape=_dev(tape))
     info = s.info()
-    assert info["fallback_rows"] >= M  # every user row has one rating
-    eu = row_rel_err(s.U.cpu().numpy(), ref["U"])
-    print(f"fallback rows {info['fallback_rows']} max U err {eu.max():.2e}")
+    assert info["fallback_rows"] >= prob.M  # every user row
+    U1 = s.U.cpu().numpy()
+    eu = row_rel_err(U1, ref["U"], MIXED_FLOOR)
     # FP64 arithmetic on FP32-stored inputs; the output is stored in FP32
-    assert eu.max() <= 1e-6
+    assert eu.max() <= 1e-6, eu.max()
+    R = prob.R
+    h = s.hyper()
+    nb = K * (K - 1) // 2
+    o = 2 * K + nb + R.M * K
+    Zv = tape[o + 2 * K + nb:o + 2 * K + nb + R.N * K].reshape(R.N, K)
+    movie_fb = info["fallback_rows"] > prob.M
+    G = bf16_round(U1) if (precision == "bf16" and not movie_fb) else U1.astype(np.float32)
+    V_ref = O.half_sweep(R.col_ptr, R.row_idx, R.col_val, G.astype(np.float64), prob.alpha, prob.mean_rating,
+                         h["Lambda_V"], h["mu_V"], Zv, nthreads=8)
+    ev = row_rel_err(s.V.cpu().numpy(), V_ref, MIXED_FLOOR)
+    print(f"{precision} K={K} {nr} ratings/user {shape}: fallback rows {info['fallback_rows']} "
+          f"max U err {eu.max():.2e} V err {ev.max():.2e}")
+    assert movie_fb == (K > 32)
+    if movie_fb:
+        assert info["fallback_rows"] == prob.M + prob.N
+        assert ev.max() <= 1e-6
+    else:
+        # FP32 rows with alpha = 1e9 and ~60 terms: n u cond(P) ~ 1e-4; a BF16
+        # copy of U that the recompute left stale would give an O(1) error
+        assert ev.max() <= 1e-2
 
 
 @pytest.mark.parametrize("precision", ["fp64", "bf16"])

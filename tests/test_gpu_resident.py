@@ -1,6 +1,8 @@
 """Resident fold-in server (one persistent kernel, request slots in pinned
-host memory): predictions bitwise equal to bpmf_foldin, the kernel's idle
-exit and relaunch, slot-size admission, and real-time replay."""
+host memory): predictions bitwise equal to bpmf_foldin and within the fold-in
+tolerance of the FP64 oracle, requests whose FP32 pivot fails recomputed in
+FP64, the kernel's idle exit and relaunch, slot-size admission, and real-time
+replay."""
 import time
 
 import numpy as np
@@ -8,7 +10,10 @@ import pytest
 
 from paper_1705_10633_amd import synth
 
-from .test_gpu_serving import _foldin, _run_direct
+from oracle import oracle as O
+
+from .test_gpu_serving import (FOLDIN_F64_TOL, FOLDIN_TOL, _foldin, _pivot_failure_model,
+                               _pivot_failure_requests, _run_direct)
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +51,36 @@ def test_resident_server_equals_foldin(S, K, N):
     ref = _run_direct(fm, req)
     for i in range(req.n):
         assert np.array_equal(got[i], ref[req.q_ptr[i]:req.q_ptr[i + 1]]), i
+    # and against the FP64 oracle
+    ora = O.foldin(model, req)
+    res = np.concatenate([got[i] for i in range(req.n)])
+    err = np.abs(res - ora) / (1.0 + np.abs(ora - model.mean_rating))
+    print(f"S={S} K={K}: resident vs oracle max scaled err {err.max():.2e}")
+    assert err.max() <= FOLDIN_TOL
+
+
+def test_resident_pivot_failure_recomputed_in_fp64():
+    """A request whose FP32 pivot fails comes back from the resident kernel as
+    NaN and is computed again in FP64 (through bpmf_foldin): the predictions
+    equal batching mode's bitwise and the FP64 oracle's to FP64 accuracy."""
+    from paper_1705_10633_amd.serving import FoldinServer
+    N, K = 2000, 32
+    model = _pivot_failure_model(8, N, K, seed=7)
+    fm = _foldin(model)
+    req = _pivot_failure_requests(N, seed=11, n=16, Q=9)
+    srv = FoldinServer(fm, resident=True, n_slots=4, max_nnz=400, max_q=16)
+    _submit_all(srv, req)
+    srv.drain()
+    got = _collect(srv, req.n)
+    srv.close()
+    ref = _run_direct(fm, req)
+    ora = O.foldin(model, req)
+    for i in range(req.n):
+        sl = slice(req.q_ptr[i], req.q_ptr[i + 1])
+        assert np.array_equal(got[i], ref[sl]), i
+        err = np.abs(got[i] - ora[sl]) / (1.0 + np.abs(ora[sl] - model.mean_rating))
+        bound = FOLDIN_F64_TOL if req.ptr[i + 1] - req.ptr[i] < K else FOLDIN_TOL
+        assert err.max() <= bound, (i, err.max())
 
 
 def test_resident_empty_request_and_slot_admission():
