@@ -280,6 +280,24 @@ bpmf_status bpmf_foldin(const bpmf_foldin_model *m, int64_t n_req, const int64_t
                         const int32_t *d_q_cols, int64_t n_queries, float *d_out, void *d_ws,
                         size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as bpmf_foldin, with the per-sample partial
+ * predictions kept in a library-owned device array instead of a caller
+ * workspace.  The array holds bpmf_foldin_noalloc_max_partials() floats
+ * (4 MiB; S * n_queries must not exceed it, else BPMF_E_INVALID before any
+ * device work); each GPU the library runs on has its own copy, held until
+ * the process ends, found on the first call on that device.  The call itself
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * Every call on one GPU uses that GPU's array and leaves its contents there;
+ * nothing in it has to start at zero.  Calls that overlap on one GPU (on
+ * streams not ordered with each other, or from several threads) race on the
+ * array; order them.  Errors: BPMF_E_INVALID, BPMF_E_HIP. */
+bpmf_status bpmf_foldin_noalloc(const bpmf_foldin_model *m, int64_t n_req, const int64_t *d_req_ptr,
+                                const int32_t *d_cols, const float *d_vals, const int64_t *d_q_ptr,
+                                const int32_t *d_q_cols, int64_t n_queries, float *d_out, void *stream);
+int64_t bpmf_foldin_noalloc_max_partials(void);
+
 /* ------------------------------------------------------------------------ */
 /* Fold-in serving engine: continuous batching on several streams             */
 /* ------------------------------------------------------------------------ */

@@ -90,6 +90,8 @@ EXPORTS = {
     "bpmf_get_timing": [P, P, I32],
     "bpmf_foldin_workspace_size": [P, I64, P],
     "bpmf_foldin": [P, I64, P, P, P, P, P, I64, P, P, SZ, P],
+    "bpmf_foldin_noalloc": [P, I64, P, P, P, P, P, I64, P, P],
+    "bpmf_foldin_noalloc_max_partials": [],
     "bpmf_server_create": [P, P, SZ, I32, I32, I32],
     "bpmf_server_create_resident": [P, P, I32, I32, I32, I64],
     "bpmf_server_submit": [P, I64, I32, P, P, I32, P],
@@ -115,7 +117,8 @@ def load(path: str = LIB_PATH):
     for name, args in EXPORTS.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = C.c_char_p if name in ("bpmf_status_string", "bpmf_last_error", "bpmf_version") else I32
+        fn.restype = (C.c_char_p if name in ("bpmf_status_string", "bpmf_last_error", "bpmf_version")
+                      else I64 if name == "bpmf_foldin_noalloc_max_partials" else I32)
     _lib = lib
     return lib
 

@@ -26,6 +26,8 @@ hipError_t launch_foldin(int S, int K, int64_t N, double alpha, double rbar, con
                          const int32_t *cols, const float *vals, const int64_t *q_ptr,
                          const int32_t *q_cols, int64_t n_queries, float *partial, float *out,
                          hipStream_t st);
+int64_t foldin_noalloc_max_partials();
+hipError_t foldin_noalloc_scratch(float **out);
 hipError_t launch_sum_values(const void *vals, int is_f64, int64_t n, double *partials, int nblk,
                              hipStream_t s);
 hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_t n,
@@ -990,6 +992,30 @@ static bpmf_status check_foldin_model(const bpmf_foldin_model *m)
     if (m->S < 1 || m->K < 1 || m->K > 64 || m->N < 1) return fail(BPMF_E_INVALID, "fold-in needs S >= 1, 1 <= K <= 64, N >= 1");
     if (!m->d_V || !m->d_Lambda || !m->d_mu) return fail(BPMF_E_INVALID, "NULL model arrays");
     if (!(m->alpha > 0.0)) return fail(BPMF_E_INVALID, "alpha must be > 0");
+    return BPMF_OK;
+}
+
+int64_t bpmf_foldin_noalloc_max_partials(void) { return foldin_noalloc_max_partials(); }
+
+bpmf_status bpmf_foldin_noalloc(const bpmf_foldin_model *m, int64_t n_req, const int64_t *d_req_ptr,
+                                const int32_t *d_cols, const float *d_vals, const int64_t *d_q_ptr,
+                                const int32_t *d_q_cols, int64_t n_queries, float *d_out, void *stream)
+{
+    bpmf_status st = check_foldin_model(m);
+    if (st != BPMF_OK) return st;
+    if (n_req < 0 || n_queries < 0) return fail(BPMF_E_INVALID, "negative sizes");
+    if ((int64_t)m->S * n_queries > foldin_noalloc_max_partials())
+        return fail(BPMF_E_INVALID, "S * n_queries = " + std::to_string((int64_t)m->S * n_queries) +
+                                        " exceeds the " + std::to_string(foldin_noalloc_max_partials()) +
+                                        " partials of the library's fold-in array");
+    if (n_req == 0) return BPMF_OK;
+    if (!d_req_ptr || !d_q_ptr || (n_queries > 0 && (!d_q_cols || !d_out)))
+        return fail(BPMF_E_INVALID, "NULL request arrays");
+    float *partial = nullptr;
+    HIP_OK(foldin_noalloc_scratch(&partial));
+    HIP_OK(launch_foldin(m->S, m->K, m->N, m->alpha, m->mean_rating, m->d_V, m->d_Lambda, m->d_mu, n_req,
+                         d_req_ptr, d_cols, d_vals, d_q_ptr, d_q_cols, n_queries, partial, d_out,
+                         (hipStream_t)stream));
     return BPMF_OK;
 }
 

@@ -11,6 +11,7 @@
 // second kernel, and a third averages the S partials in sample order.
 // Nothing a wavefront computes depends on the other requests of the batch.
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 #include "rowsolve.hpp"
@@ -220,6 +221,36 @@ __global__ void foldin_reduce_kernel(int S, float rbar, const float *partial, in
 }
 
 }  // namespace
+
+// Device-resident partials for bpmf_foldin_noalloc: a file-scope array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address); it looks up each device's address once, with that device
+// current, and passes that.
+constexpr int64_t kNoallocPartials = int64_t(1) << 20;  // floats (4 MiB)
+static __device__ __align__(256) float scratch[kNoallocPartials];
+
+int64_t foldin_noalloc_max_partials() { return kNoallocPartials; }
+
+hipError_t foldin_noalloc_scratch(float **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static float *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = (float *)p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_foldin(int S, int K, int64_t N, double alpha, double rbar, const float *Vs,
                          const double *Lam, const double *mu, int64_t n_req, const int64_t *req_ptr,

@@ -211,3 +211,12 @@ class Foldin:
         call("bpmf_foldin", C.byref(self.model), n_req, _ptr(ptr), _ptr(cols), _ptr(vals), _ptr(q_ptr),
              _ptr(q_cols), n_q, _ptr(out), _ptr(ws), C.c_size_t(ws.numel()), _stream(torch, stream))
         return out[:n_q]
+
+    def run_noalloc(self, ptr, cols, vals, q_ptr, q_cols, out, stream=None):
+        """bpmf_foldin_noalloc: the same as run() with the partials in the
+        library's own device array (no workspace, nothing allocated)."""
+        n_req = int(ptr.numel()) - 1
+        n_q = int(q_cols.numel())
+        call("bpmf_foldin_noalloc", C.byref(self.model), n_req, _ptr(ptr), _ptr(cols), _ptr(vals), _ptr(q_ptr),
+             _ptr(q_cols), n_q, _ptr(out), _stream(self.torch, stream))
+        return out[:n_q]

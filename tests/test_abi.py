@@ -139,6 +139,13 @@ def test_foldin_and_server_argument_checks(lib):
     assert lib.bpmf_server_create(C.byref(srv), C.byref(bad), 1 << 20, 2, 8, 8) == 1
     assert lib.bpmf_server_create(C.byref(srv), C.byref(m), 1 << 20, 0, 8, 8) == 1     # no streams
     assert lib.bpmf_server_create(C.byref(srv), C.byref(m), 64, 1, 8, 8) == 1          # budget too small
+    # the no-allocation fold-in refuses what its fixed array cannot hold, before any device work
+    cap = lib.bpmf_foldin_noalloc_max_partials()
+    assert cap == 1 << 20
+    assert lib.bpmf_foldin_noalloc(C.byref(m), 1, fake, fake, fake, fake, fake, cap // 16 + 1, fake, None) == 1
+    assert lib.bpmf_foldin_noalloc(C.byref(bad), 1, fake, fake, fake, fake, fake, 1, fake, None) == 1
+    assert lib.bpmf_foldin_noalloc(C.byref(m), -1, fake, fake, fake, fake, fake, 1, fake, None) == 1
+    assert lib.bpmf_foldin_noalloc(C.byref(m), 0, None, None, None, None, None, 0, None, None) == 0
 
 
 def test_launch_shape_fields_are_validated(lib):
