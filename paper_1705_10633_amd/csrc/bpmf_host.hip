@@ -68,7 +68,7 @@ struct WsLayout {
 
 struct Offsets {
     size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], lamacc[2], lchol[2], nwd[2], mu0, w0inv,
-        order[2], rowtab[2], ctab[2], part[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
+        order[2], rowtab[2], recoff[2], rec[2], ctab[2], part[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
 
@@ -140,7 +140,14 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
         o.order[s] = w.add(sizeof(int32_t) * n[s]);
         // launch table: the rows, or (with heavy rows) their pieces and then the other rows
         const bool pieces = mk && K <= 64;
-        o.rowtab[s] = w.add(sizeof(int4) * (n[s] + (pieces ? kMaxPieces : 0)));
+        const int64_t n_entries = n[s] + (pieces ? kMaxPieces : 0);
+        o.rowtab[s] = w.add(sizeof(int4) * n_entries);
+        // BF16 packed rating records: each entry padded to whole chunks, so at
+        // most nnz + n_entries (chunk - 1) ratings, 8 bytes each
+        const bool recs = mk && p->precision == BPMF_BF16;
+        const int64_t chunk = bf16_chunk(padded_k(K));
+        o.recoff[s] = w.add(recs ? sizeof(int64_t) * n_entries : 0);
+        o.rec[s] = w.add(recs ? 8 * (size_t)(R->nnz + n_entries * (chunk - 1) + 4) : 0);
         o.ctab[s] = w.add(pieces ? sizeof(int4) * kMaxPieces / 2 : 0);
         o.part[s] = w.add(pieces ? sizeof(float) * (size_t)kMaxPieces * piece_floats(padded_k(K)) : 0);
         o.fblist[s] = w.add(mk ? sizeof(int32_t) * n[s] : 0);
@@ -176,6 +183,9 @@ struct bpmf_ctx {
     // head of the row order: heavy rows cut into pieces (K <= 64); the launch
     // table holds n_pieces pieces and then the rows from slot n_heavy on
     int64_t n_heavy[2] = {0, 0}, n_pieces[2] = {0, 0};
+    // entries of the launch table per side (pieces and rows)
+    int64_t n_entries[2] = {0, 0};
+    bool records = false;  // BF16 mode: the row kernels read packed rating records
     int64_t n_test;
     const int32_t *test_rows, *test_cols;
     hipGraph_t graph = nullptr;
@@ -441,6 +451,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
     c->rbar = rbar;
 
     const LaunchShape shape = resolve_shape(p->shape, K);
+    c->records = p->precision == BPMF_BF16 && mixed_supported(K, p->precision);
     // row order: rating count descending, ties by index
     for (int sd = 0; sd < 2; ++sd) {
         std::vector<int32_t> ord(n[sd]);
@@ -504,8 +515,22 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         c->n_heavy[sd] = nh;
         c->n_pieces[sd] = (int64_t)tab.size();
         for (int64_t q = nh; q < n[sd]; ++q) tab.push_back(entry(q));
+        c->n_entries[sd] = (int64_t)tab.size();
         HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.rowtab[sd]), tab.data(), sizeof(int4) * tab.size(),
                                 hipMemcpyHostToDevice, s));
+        if (c->records) {
+            // first record of every entry (records are built once the FP32 ratings exist)
+            const int64_t chunk = bf16_chunk(c->KP);
+            std::vector<int64_t> roff(tab.size());
+            int64_t g = 0;
+            for (size_t e = 0; e < tab.size(); ++e) {
+                roff[e] = g;
+                g += (tab[e].y + chunk - 1) / chunk * (chunk / 4);
+            }
+            HIP_OK_C(hipMemcpyAsync(c->at<int64_t>(off.recoff[sd]), roff.data(), sizeof(int64_t) * roff.size(),
+                                    hipMemcpyHostToDevice, s));
+            HIP_OK_C(hipStreamSynchronize(s));
+        }
         if (!ctab.empty())
             HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.ctab[sd]), ctab.data(), sizeof(int4) * ctab.size(),
                                     hipMemcpyHostToDevice, s));
@@ -545,6 +570,18 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         HIP_OK_C(launch_f64_to_f32((const double *)R->d_row_val, c->at<float>(off.valsf[0]), R->nnz, s));
         HIP_OK_C(launch_f64_to_f32((const double *)R->d_col_val, c->at<float>(off.valsf[1]), R->nnz, s));
     }
+    // packed rating records of the BF16 row kernels
+    if (c->records)
+        for (int sd = 0; sd < 2; ++sd) {
+            SideArgs a{};
+            a.n_other = sd == 0 ? R->N : R->M;
+            a.idx = sd == 0 ? R->d_col_idx : R->d_row_idx;
+            a.val = R->val_is_f64 ? (const void *)c->at<float>(off.valsf[sd]) : (sd == 0 ? R->d_row_val : R->d_col_val);
+            a.rowtab = c->at<int4>(off.rowtab[sd]);
+            a.recoff = c->at<int64_t>(off.recoff[sd]);
+            HIP_OK_C(launch_build_records(a, c->n_entries[sd], bf16_chunk(c->KP), (float)rbar,
+                                          c->at<uint4>(off.rec[sd]), s));
+        }
     // BF16 copies of the initial factors
     if (p->precision == BPMF_BF16 && mixed_supported(K, p->precision)) {
         HIP_OK_C(launch_to_bf16((const float *)d_U, R->M, K, c->KP, c->at<uint16_t>(off.shadow[0]), s));
@@ -664,6 +701,8 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
     a.other = side == 0 ? c->dV : c->dU;
     a.order = c->at<int32_t>(c->off.order[side]);
     a.rowtab = c->at<int4>(c->off.rowtab[side]);
+    a.rec = c->records ? c->at<uint4>(c->off.rec[side]) : nullptr;
+    a.recoff = c->records ? c->at<int64_t>(c->off.recoff[side]) : nullptr;
     a.shadow_stride = c->KP;
     hipEvent_t t0;
     if (f64) {

@@ -75,7 +75,21 @@ struct SideArgs {
     // per order slot {row, rating count, first rating (low, high word)}: one
     // 16-byte load instead of the order entry and then the row pointers
     const int4 *rowtab;
+    // BF16 mode: the ratings of each launch-table entry as packed records,
+    // one 32-byte record per 4 ratings: {4 column indices} then the offsets
+    // r' = r - rbar of the 4 ratings as two BF16 parts hi = bf16(r'),
+    // lo = bf16(r' - hi), packed {hi0 | hi1 << 16, hi2 | hi3 << 16,
+    // lo0 | lo1 << 16, lo2 | lo3 << 16}.  Every entry is padded to a multiple
+    // of the kernel's chunk with records of the all-zero row and r' = 0, so
+    // the gathers need no bounds.  Entry e starts at record recoff[e]
+    // (uint4 rec[2 * recoff[e]]).  NULL outside BF16 mode.
+    const uint4 *rec;
+    const int64_t *recoff;
 };
+
+// Ratings per chunk of the BF16 row kernels, which each entry's records are
+// padded to: KP = 32 and 128: 64; KP = 64: 32.
+__host__ __device__ constexpr int bf16_chunk(int KP) { return KP == 64 ? 32 : 64; }
 
 // Masked loads are written as an unconditional load (from a clamped, valid
 // index) scaled or blended by the mask, so the compiler does not put each
@@ -173,6 +187,10 @@ hipError_t launch_rows_tiny(const SideArgs &a, int K, int bf16, double alpha, do
 hipError_t launch_rows_rank1(const SideArgs &a, int K, int KP, int bf16, double alpha, double rbar, HyperDev hyp,
                              DrawSrc draws, int32_t *fb_list, DevState *state, int64_t slot0, int64_t slot1,
                              int64_t nnz, hipStream_t s);
+// Packed rating records (SideArgs::rec) of n_entries launch-table entries of
+// a.rowtab, each padded to a multiple of `chunk` ratings.
+hipError_t launch_build_records(const SideArgs &a, int64_t n_entries, int chunk, float rbar, uint4 *rec,
+                                hipStream_t s);
 hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, double rbar,
                           int64_t n, const int32_t *rows, const int32_t *cols, double *out,
                           double *accum, const DevState *state, int burnin, hipStream_t s);

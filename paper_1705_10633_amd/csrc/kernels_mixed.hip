@@ -71,8 +71,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         row = rt.x;
         const int64_t s0 = (int64_t)(((uint64_t)(uint32_t)rt.w << 32) | (uint32_t)rt.z), s1 = s0 + rt.y;
         if constexpr (BF16)
-            gram_bf16<KP>(a.idx + s0, vals + s0, s1 - s0, a.other_bf16, a.shadow_stride, (int32_t)a.n_other,
-                          rbar, (char *)u, (uint32_t *)rv, acc, bacc);
+            gram_bf16<KP>(a.rec + 2 * a.recoff[blockIdx.x], s1 - s0, a.other_bf16, a.shadow_stride, (char *)u,
+                          (uint32_t *)rv, acc, bacc);
         else
             gram_f32<KP>(a.idx + s0, vals + s0, s1 - s0, (const float *)a.other, K, rbar, u, rv,
                          sidx, acc, bacc);
@@ -123,7 +123,45 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
 }
 
+// One workgroup per launch-table entry: its ratings as packed records (see
+// SideArgs::rec), padded to a multiple of `chunk` ratings.  r' = r - rbar and
+// its BF16 parts are formed exactly as a row kernel would form them from the
+// FP32 rating, so the records change no result.
+__global__ __launch_bounds__(256) void build_records_kernel(const int4 *rowtab, const int64_t *recoff,
+                                                            const int32_t *idx, const float *vals, float rbar,
+                                                            int32_t sentinel, int chunk, uint4 *rec)
+{
+    const int4 rt = rowtab[blockIdx.x];
+    const int64_t s0 = (int64_t)(((uint64_t)(uint32_t)rt.w << 32) | (uint32_t)rt.z), cnt = rt.y;
+    const int64_t groups = (cnt + chunk - 1) / chunk * (chunk / 4);
+    uint4 *out = rec + 2 * recoff[blockIdx.x];
+    for (int64_t g = threadIdx.x; g < groups; g += blockDim.x) {
+        uint32_t c[4], hi[4], lo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t n = 4 * g + q;
+            const bool ok = n < cnt;
+            c[q] = ok ? (uint32_t)idx[s0 + n] : (uint32_t)sentinel;
+            const float v = ok ? vals[s0 + n] - rbar : 0.0f;
+            hi[q] = f32_to_bf16_rne(v);
+            lo[q] = f32_to_bf16_rne(v - bf16_to_f32((uint16_t)hi[q]));
+        }
+        out[2 * g] = make_uint4(c[0], c[1], c[2], c[3]);
+        out[2 * g + 1] = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16), lo[0] | (lo[1] << 16),
+                                    lo[2] | (lo[3] << 16));
+    }
+}
+
 }  // namespace
+
+hipError_t launch_build_records(const SideArgs &a, int64_t n_entries, int chunk, float rbar, uint4 *rec,
+                                hipStream_t s)
+{
+    if (n_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(build_records_kernel, dim3((unsigned)n_entries), dim3(256), 0, s, a.rowtab, a.recoff, a.idx,
+                       (const float *)a.val, rbar, (int32_t)a.n_other, chunk, rec);
+    return hipGetLastError();
+}
 
 int heavy_min_ratings() { return 2048; }
 

@@ -72,14 +72,12 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int4 rt = sa.rowtab[blockIdx.x];
     const int row = rt.x;
-    const int64_t s0 = (int64_t)(((uint64_t)(uint32_t)rt.w << 32) | (uint32_t)rt.z), s1 = s0 + rt.y;
-    const int64_t nnz = s1 - s0;
-    const int32_t *idx = sa.idx + s0;
-    const float *vals = (const float *)sa.val + s0;
+    const int64_t nnz = rt.y;
     const uint16_t *src = sa.other_bf16;
-    const int32_t sentinel = (int32_t)sa.n_other;
 
     // ---------------- Gram (matrix cores) and right-hand side ----------------
+    // Records (SideArgs::rec, padded to 64-rating chunks): per 4 ratings the
+    // column indices and the two-part BF16 offsets r - rbar.
     const int ntile = wave < 2 ? 3 : 2;
     floatx16 acc[3];
 #pragma unroll
@@ -89,34 +87,17 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     float bacc = 0.0f;
     char *stage = (char *)u;
     const int fb = tid / RG2, rg = tid % RG2;
-    auto load_idx = [&](int64_t c0, int *j) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t n = c0 + rg * 4 + q;
-            j[q] = idx[n < nnz ? n : nnz - 1];
-        }
+    static_assert(CH2 == bf16_chunk(K2), "records are padded to the kernel's chunk");
+    auto load_rows = [&](const uint4 &c, uint4 *d) {
+        d[0] = *(const uint4 *)(src + (int64_t)(int)c.x * K2 + fb * 8);
+        d[1] = *(const uint4 *)(src + (int64_t)(int)c.y * K2 + fb * 8);
+        d[2] = *(const uint4 *)(src + (int64_t)(int)c.z * K2 + fb * 8);
+        d[3] = *(const uint4 *)(src + (int64_t)(int)c.w * K2 + fb * 8);
     };
-    auto load_rows = [&](int64_t c0, const int *j, uint4 *d, float *v) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t n = c0 + rg * 4 + q;
-            const int jj = blend_idx(n < nnz, j[q], sentinel);
-            d[q] = *(const uint4 *)(src + (int64_t)jj * K2 + fb * 8);
-            v[q] = vals[n < nnz ? n : nnz - 1];
-        }
-    };
-    auto stage_chunk = [&](int64_t c0, const uint4 *d, const float *vraw) {
+    auto stage_chunk = [&](const uint4 *d, const uint4 &rp) {
         if (fb == 0) {
-            uint32_t hi[4], lo[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t n = c0 + rg * 4 + q;
-                const float v = (vraw[q] - rbar) * (n < nnz ? 1.0f : 0.0f);
-                hi[q] = f32_to_bf16_rne(v);
-                lo[q] = f32_to_bf16_rne(v - bf16_to_f32((uint16_t)hi[q]));
-            }
-            *(uint2 *)(rvp + rg * 2) = make_uint2(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16));
-            *(uint2 *)(rvp + CH2 / 2 + rg * 2) = make_uint2(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16));
+            *(uint2 *)(rvp + rg * 2) = make_uint2(rp.x, rp.y);
+            *(uint2 *)(rvp + CH2 / 2 + rg * 2) = make_uint2(rp.z, rp.w);
         }
         const uint32_t w0[4] = {d[0].x, d[0].y, d[0].z, d[0].w};
         const uint32_t w1[4] = {d[1].x, d[1].y, d[1].z, d[1].w};
@@ -150,33 +131,48 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             }
         }
         if (tid < K2) {
-            const uint32_t *sp = (const uint32_t *)(stage + tid * SB2);
+            const uint4 *sp = (const uint4 *)(stage + tid * SB2);
+            const uint4 *hp = (const uint4 *)rvp, *lp = (const uint4 *)(rvp + CH2 / 2);
 #pragma unroll
-            for (int p = 0; p < CH2 / 2; ++p) {
-                bf16x2_t x, yh, yl;
-                const uint32_t sv = sp[p], hv = rvp[p], lv = rvp[CH2 / 2 + p];
-                __builtin_memcpy(&x, &sv, 4);
-                __builtin_memcpy(&yh, &hv, 4);
-                __builtin_memcpy(&yl, &lv, 4);
-                bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yh, bacc, false);
-                bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yl, bacc, false);
+            for (int p4 = 0; p4 < CH2 / 8; ++p4) {
+                const uint4 sv = sp[p4], hv = hp[p4], lv = lp[p4];
+                const uint32_t sa4[4] = {sv.x, sv.y, sv.z, sv.w};
+                const uint32_t ha[4] = {hv.x, hv.y, hv.z, hv.w};
+                const uint32_t la[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    bf16x2_t x, yh, yl;
+                    __builtin_memcpy(&x, &sa4[q], 4);
+                    __builtin_memcpy(&yh, &ha[q], 4);
+                    __builtin_memcpy(&yl, &la[q], 4);
+                    bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yh, bacc, false);
+                    bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yl, bacc, false);
+                }
             }
         }
     };
     {
-        int j[4];
-        uint4 d[4];
-        float v[4];
-        if (nnz > 0) {
-            load_idx(0, j);
-            load_rows(0, j, d, v);
-            if (CH2 < nnz) load_idx(CH2, j);
+        const int64_t nch = (nnz + CH2 - 1) / CH2;
+        const uint4 *r0 = sa.rec + 2 * (sa.recoff[blockIdx.x] + rg);
+        uint4 d[4], rpc, nc, nr;
+        if (nch > 0) {
+            nc = r0[0];
+            rpc = r0[1];
+            load_rows(nc, d);
+            if (nch > 1) {
+                nc = r0[2 * RG2];
+                nr = r0[2 * RG2 + 1];
+            }
         }
-        for (int64_t c0 = 0; c0 < nnz; c0 += CH2) {
-            stage_chunk(c0, d, v);
-            if (c0 + CH2 < nnz) {
-                load_rows(c0 + CH2, j, d, v);
-                if (c0 + 2 * CH2 < nnz) load_idx(c0 + 2 * CH2, j);
+        for (int64_t c = 0; c < nch; ++c) {
+            stage_chunk(d, rpc);
+            if (c + 1 < nch) {
+                load_rows(nc, d);
+                rpc = nr;
+                if (c + 2 < nch) {
+                    nc = r0[2 * RG2 * (c + 2)];
+                    nr = r0[2 * RG2 * (c + 2) + 1];
+                }
             }
             __syncthreads();
             multiply_chunk();

@@ -50,58 +50,43 @@ struct WaveSync {
     static __device__ __forceinline__ void sync() { __asm__ volatile("" ::: "memory"); }
 };
 
-// BF16 gathers: rows `idx[0..nnz)` of `src` (BF16, row stride `stride`,
-// 16-byte aligned rows) with ratings `vals` (FP32).  Row `sentinel` of `src`
-// is all zeros; positions past nnz gather it, so no load needs a lane mask.
-// The chunk is staged feature-major so each lane's matrix-core operand (8
-// consecutive nnz of one feature) is one 16-byte LDS read.
+// BF16 gathers of a row's rated rows of `src` (BF16, row stride `stride`,
+// 16-byte aligned rows) from the row's packed records `rec` (see
+// SideArgs::rec: per 4 ratings the column indices and the two-part BF16
+// offsets r - rbar; padded to whole chunks with the all-zero row and r' = 0,
+// so no load needs a bound or a lane mask).  Each lane fetches
+// one 16-byte piece of 4 rated rows per chunk.  The chunk is staged
+// feature-major so each lane's matrix-core operand (8 consecutive ratings of
+// one feature) is one 16-byte LDS read.
 //
 // The right-hand side sum_j r'_j v_j runs on v_dot2c_f32_bf16 over pairs of
-// ratings, with r' = r - rbar split into two BF16 parts hi = bf16(r') and
-// lo = bf16(r' - hi), so r' is carried to about 2^-17 relative; `rvp` holds
-// CH / 2 packed hi pairs followed by CH / 2 lo pairs.
+// ratings with r' = hi + lo carried to about 2^-17 relative; `rvp` holds the
+// chunk's CH / 2 packed hi pairs followed by its CH / 2 lo pairs.
 template <int KP, class Sync = BlockSync>
-__device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals, int64_t nnz,
-                                          const uint16_t *src, int stride, int32_t sentinel, float rbar,
+__device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const uint16_t *src, int stride,
                                           char *stage, uint32_t *rvp, floatx16 *acc, float &bacc)
 {
     using S = RowShape<KP>;
+    static_assert(S::CH == bf16_chunk(KP), "records are padded to the kernel's chunk");
     const int lane = threadIdx.x & 63;
     // lanes 0..RG-1 stage feature block 0, lanes RG..2RG-1 block 1, ...: the
     // 8-byte staging writes of a quarter-wave then spread over more banks
     // than with consecutive lanes on consecutive feature blocks
     const int fb = lane / S::RG, rg = lane % S::RG;
+    const int64_t nch = (nnz + S::CH - 1) / S::CH;
     // Loaded values stay raw until they are used (a chunk later), so no
     // arithmetic right after a load forces a wait for the loads in flight.
-    auto load_idx = [&](int64_t c0, int *j) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t n = c0 + rg * 4 + q;
-            j[q] = idx[n < nnz ? n : nnz - 1];
-        }
+    auto load_rows = [&](const uint4 &c, uint4 *d) {
+        d[0] = *(const uint4 *)(src + (int64_t)(int)c.x * stride + fb * 8);
+        d[1] = *(const uint4 *)(src + (int64_t)(int)c.y * stride + fb * 8);
+        d[2] = *(const uint4 *)(src + (int64_t)(int)c.z * stride + fb * 8);
+        d[3] = *(const uint4 *)(src + (int64_t)(int)c.w * stride + fb * 8);
     };
-    auto load_rows = [&](int64_t c0, const int *j, uint4 *d, float *v) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t n = c0 + rg * 4 + q;
-            const int jj = blend_idx(n < nnz, j[q], sentinel);
-            d[q] = *(const uint4 *)(src + (int64_t)jj * stride + fb * 8);
-            v[q] = vals[n < nnz ? n : nnz - 1];
-        }
-    };
-    // r' halves and the feature-major copy of one chunk into LDS
-    auto stage_chunk = [&](int64_t c0, const uint4 *d, const float *vraw) {
+    // r' pairs and the feature-major copy of one chunk into LDS
+    auto stage_chunk = [&](const uint4 *d, const uint4 &rp) {
         if (fb == 0) {
-            uint32_t hi[4], lo[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t n = c0 + rg * 4 + q;
-                const float v = (vraw[q] - rbar) * (n < nnz ? 1.0f : 0.0f);
-                hi[q] = f32_to_bf16_rne(v);
-                lo[q] = f32_to_bf16_rne(v - bf16_to_f32((uint16_t)hi[q]));
-            }
-            *(uint2 *)(rvp + rg * 2) = make_uint2(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16));
-            *(uint2 *)(rvp + S::CH / 2 + rg * 2) = make_uint2(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16));
+            *(uint2 *)(rvp + rg * 2) = make_uint2(rp.x, rp.y);
+            *(uint2 *)(rvp + S::CH / 2 + rg * 2) = make_uint2(rp.z, rp.w);
         }
         const uint32_t w0[4] = {d[0].x, d[0].y, d[0].z, d[0].w};
         const uint32_t w1[4] = {d[1].x, d[1].y, d[1].z, d[1].w};
@@ -134,37 +119,52 @@ __device__ __forceinline__ void gram_bf16(const int32_t *idx, const float *vals,
         }
         constexpr int SPLIT = 64 / KP;
         constexpr int PAIRS = S::CH / SPLIT / 2;
+        static_assert(PAIRS % 4 == 0, "rhs pairs are read four at a time");
         const int f = lane % KP, part = lane / KP;
-        const uint32_t *sp = (const uint32_t *)(stage + f * S::SB) + part * PAIRS;
-        const uint32_t *hp = rvp + part * PAIRS, *lp = rvp + S::CH / 2 + part * PAIRS;
+        const uint4 *sp = (const uint4 *)(stage + f * S::SB) + part * (PAIRS / 4);
+        const uint4 *hp = (const uint4 *)rvp + part * (PAIRS / 4);
+        const uint4 *lp = (const uint4 *)(rvp + S::CH / 2) + part * (PAIRS / 4);
 #pragma unroll
-        for (int p = 0; p < PAIRS; ++p) {
-            bf16x2_t x, yh, yl;
-            const uint32_t sv = sp[p], hv = hp[p], lv = lp[p];
-            __builtin_memcpy(&x, &sv, 4);
-            __builtin_memcpy(&yh, &hv, 4);
-            __builtin_memcpy(&yl, &lv, 4);
-            bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yh, bacc, false);
-            bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yl, bacc, false);
+        for (int p4 = 0; p4 < PAIRS / 4; ++p4) {
+            const uint4 sv = sp[p4], hv = hp[p4], lv = lp[p4];
+            const uint32_t sa[4] = {sv.x, sv.y, sv.z, sv.w};
+            const uint32_t ha[4] = {hv.x, hv.y, hv.z, hv.w};
+            const uint32_t la[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                bf16x2_t x, yh, yl;
+                __builtin_memcpy(&x, &sa[q], 4);
+                __builtin_memcpy(&yh, &ha[q], 4);
+                __builtin_memcpy(&yl, &la[q], 4);
+                bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yh, bacc, false);
+                bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yl, bacc, false);
+            }
         }
     };
     // Software pipeline with one register set: as soon as a chunk is staged,
-    // the rows of the next chunk (whose indices are already loaded) and the
-    // indices of the one after are requested, and they arrive while the
+    // the rows of the next chunk (whose records are already loaded) and the
+    // records of the one after are requested, and they arrive while the
     // staged chunk is multiplied.
-    int j[4];
-    uint4 d[4];
-    float v[4];
-    if (nnz > 0) {
-        load_idx(0, j);
-        load_rows(0, j, d, v);
-        if (S::CH < nnz) load_idx(S::CH, j);
+    const uint4 *r0 = rec + 2 * rg;
+    uint4 d[4], rpc, nc, nr;
+    if (nch > 0) {
+        nc = r0[0];
+        rpc = r0[1];
+        load_rows(nc, d);
+        if (nch > 1) {
+            nc = r0[2 * S::RG];
+            nr = r0[2 * S::RG + 1];
+        }
     }
-    for (int64_t c0 = 0; c0 < nnz; c0 += S::CH) {
-        stage_chunk(c0, d, v);
-        if (c0 + S::CH < nnz) {
-            load_rows(c0 + S::CH, j, d, v);
-            if (c0 + 2 * S::CH < nnz) load_idx(c0 + 2 * S::CH, j);
+    for (int64_t c = 0; c < nch; ++c) {
+        stage_chunk(d, rpc);
+        if (c + 1 < nch) {
+            load_rows(nc, d);
+            rpc = nr;
+            if (c + 2 < nch) {
+                nc = r0[2 * S::RG * (c + 2)];
+                nr = r0[2 * S::RG * (c + 2) + 1];
+            }
         }
         Sync::sync();
         multiply_chunk();
