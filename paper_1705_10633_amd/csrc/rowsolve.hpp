@@ -288,27 +288,31 @@ __device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *
     }
 }
 
-// A22 -= L21 L21^T for KP = 64, where lane 32 + r holds row r of L21 in
-// A[0..31] and row r of A22 in A[32..63].  The 32 x 32 x 32 product runs as
-// 16 rank-2 steps of v_mfma_f32_32x32x2_f32: the operand of step kk has
-// L21[:, 2kk] in lanes 0-31 and L21[:, 2kk + 1] in lanes 32-63, which one
-// permlane32 swap of A[2kk] and A[2kk + 1] produces.  Result register
-// 4j + i of lane l holds C[8j + 4(l / 32) + i][l % 32]; C is symmetric, so
-// lane 32 + r owns C[r][8j + 4 + i] and receives C[r][8j + i] from lane r by
-// a second swap.  Lanes 0-31 update entries right of their diagonal, which
-// are never read.
-__device__ __forceinline__ void syrk_trailing(float *A)
+// Matrix-core updates of the KP = 64 factorisation, where lane i holds row i
+// of the matrix in A[0..63] (registers).  They run as rank-2 steps of
+// v_mfma_f32_32x32x2_f32, whose operand lane l holds element (l % 32, l / 32)
+// of a 32 x 2 block and whose result register 4j + i of lane l holds
+// C[8j + 4(l / 32) + i][l % 32].  One v_permlane32_swap of two columns
+// (registers) moves a 32-row block's two columns into the operand layout.
+//
+// Rows 32..63 (lanes 32..63), columns 32 + 8j + .. for j >= JMIN:
+//   A[32 + c] -= sum_{k in K0..K0+NK-1} X[r][k] X[c][k],  X = rows 32..63.
+// C = X X^T is symmetric, so lane 32 + r already holds C[r][8j + 4 + i]
+// and receives C[r][8j + i] from lane r by a second swap.  Lanes 0..31
+// update entries right of their diagonal, which are never read.
+template <int K0, int NK, int JMIN>
+__device__ __forceinline__ void syrk_lower_rows(float *A)
 {
     floatx16 c = {};
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[2 * kk]),
-                                                         __float_as_uint(A[2 * kk + 1]), false, false);
+    for (int kk = 0; kk < NK / 2; ++kk) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[K0 + 2 * kk]),
+                                                         __float_as_uint(A[K0 + 2 * kk + 1]), false, false);
         const float x = __uint_as_float(sw[1]);
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(x, x, c, 0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = JMIN; j < 4; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float own = c[4 * j + i];
@@ -319,20 +323,42 @@ __device__ __forceinline__ void syrk_trailing(float *A)
         }
 }
 
+// All 64 rows, columns 16..31 from the first 16 columns:
+//   A[r][c] -= sum_{k < 16} L[r][k] L[c][k]   (c = 16..31).
+// D0 = L[0..31] L[0..31]^T and D1 = L[0..31] L[32..63]^T, both with the
+// column index c in the result's row position, so lane r (r < 32) holds
+// D0[8j + i][r] and lane 32 + r holds D1[8j + 4 + i][r]; one swap per result
+// register hands each lane the other half of its row.
+__device__ __forceinline__ void gemm_cols16_31(float *A)
+{
+    floatx16 d0 = {}, d1 = {};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[2 * kk]), __float_as_uint(A[2 * kk + 1]),
+                                                         false, false);
+        const float xa = __uint_as_float(sw[0]), xb = __uint_as_float(sw[1]);
+        d0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xa, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xb, d1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 2; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(d0[4 * j + i]),
+                                                             __float_as_uint(d1[4 * j + i]), false, false);
+            A[8 * j + i] -= __uint_as_float(sw[0]);
+            A[8 * j + 4 + i] -= __uint_as_float(sw[1]);
+        }
+}
 
-// Factor the KP x KP matrix whose row ri = lane % KP is in A (registers):
-// afterwards A holds row ri of L (lower, L L^T = P) and invbuf[k] = 1/L_kk.
-// `pbuf` is KP x 12 floats of LDS scratch.
-//
-// The factorisation runs in panels of 8 columns: inside a panel, column k is
-// scaled by 1/sqrt(P_kk) (lane k thereby holds L_kk) and the later panel
-// columns are updated with values read across lanes with readlane; then every
-// lane publishes its 8 panel entries through LDS once and applies the rank-8
-// update to its trailing columns.  Entries right of the diagonal are updated
-// too but never read, so the loops need no lane masks.  An unusable pivot
-// gives a NaN, infinite or zero 1/sqrt, caught by chol_pivots_fail.
-template <int KP, class Sync = BlockSync>
-__device__ __forceinline__ void chol_factor(float (&A)[KP], float *invbuf, float *pbuf)
+// Columns c0..c0+7 of the matrix whose row ri = lane % KP is in A: column k
+// is scaled by 1/sqrt(P_kk) (lane k thereby holds L_kk, invbuf[k] = 1/L_kk)
+// and the later panel columns are updated with values read across lanes with
+// readlane; then, when jend > c0 + 8, every lane publishes its 8 panel
+// entries through LDS (`pbuf`) and applies the rank-8 update to its columns
+// c0 + 8 .. jend - 1.
+template <int KP, class Sync>
+__device__ __forceinline__ void chol_panel(float (&A)[KP], float *invbuf, float *pbuf, int c0, int jend)
 {
     constexpr int PW = 8;
     // pbuf rows are 12 floats apart, so 16 consecutive lanes cover all 64
@@ -340,45 +366,73 @@ __device__ __forceinline__ void chol_factor(float (&A)[KP], float *invbuf, float
     constexpr int PS = 12;
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int c0 = 0; c0 < KP; c0 += PW) {
+    for (int k = c0; k < c0 + PW; ++k) {
+        const float inv = __builtin_amdgcn_rsqf(readlane_f(A[k], k));
+        A[k] *= inv;
+        invbuf[k] = inv;
 #pragma unroll
-        for (int k = c0; k < c0 + PW; ++k) {
-            const float inv = __builtin_amdgcn_rsqf(readlane_f(A[k], k));
-            A[k] *= inv;
-            invbuf[k] = inv;
-#pragma unroll
-            for (int j = k + 1; j < c0 + PW; ++j) A[j] = fmaf(-A[k], readlane_f(A[k], j), A[j]);
+        for (int j = k + 1; j < c0 + PW; ++j) A[j] = fmaf(-A[k], readlane_f(A[k], j), A[j]);
+    }
+    if (c0 + PW < jend) {
+        if (lane < KP) {
+            *(float4 *)(pbuf + lane * PS) = make_float4(A[c0], A[c0 + 1], A[c0 + 2], A[c0 + 3]);
+            *(float4 *)(pbuf + lane * PS + 4) = make_float4(A[c0 + 4], A[c0 + 5], A[c0 + 6], A[c0 + 7]);
         }
-        // With KP = 64 the panels of the first 32 columns update only columns
-        // below 32 here; their update of the trailing 32 x 32 block is one
-        // matrix-core product after the fourth panel (syrk_trailing).
-        constexpr int HALF = KP == 64 ? 32 : KP;
-        const int jend = c0 < HALF ? HALF : KP;
-        if (c0 + PW < jend) {
-            if (lane < KP) {
-                *(float4 *)(pbuf + lane * PS) = make_float4(A[c0], A[c0 + 1], A[c0 + 2], A[c0 + 3]);
-                *(float4 *)(pbuf + lane * PS + 4) = make_float4(A[c0 + 4], A[c0 + 5], A[c0 + 6], A[c0 + 7]);
-            }
-            Sync::sync();
+        Sync::sync();
 #pragma unroll
-            for (int j = c0 + PW; j < jend; ++j) {
-                const float4 p0 = *(const float4 *)(pbuf + j * PS);
-                const float4 p1 = *(const float4 *)(pbuf + j * PS + 4);
-                float t = A[j];
-                t = fmaf(-A[c0 + 0], p0.x, t);
-                t = fmaf(-A[c0 + 1], p0.y, t);
-                t = fmaf(-A[c0 + 2], p0.z, t);
-                t = fmaf(-A[c0 + 3], p0.w, t);
-                t = fmaf(-A[c0 + 4], p1.x, t);
-                t = fmaf(-A[c0 + 5], p1.y, t);
-                t = fmaf(-A[c0 + 6], p1.z, t);
-                t = fmaf(-A[c0 + 7], p1.w, t);
-                A[j] = t;
-            }
-            Sync::sync();
+        for (int j = c0 + PW; j < jend; ++j) {
+            const float4 p0 = *(const float4 *)(pbuf + j * PS);
+            const float4 p1 = *(const float4 *)(pbuf + j * PS + 4);
+            float t = A[j];
+            t = fmaf(-A[c0 + 0], p0.x, t);
+            t = fmaf(-A[c0 + 1], p0.y, t);
+            t = fmaf(-A[c0 + 2], p0.z, t);
+            t = fmaf(-A[c0 + 3], p0.w, t);
+            t = fmaf(-A[c0 + 4], p1.x, t);
+            t = fmaf(-A[c0 + 5], p1.y, t);
+            t = fmaf(-A[c0 + 6], p1.z, t);
+            t = fmaf(-A[c0 + 7], p1.w, t);
+            A[j] = t;
         }
-        if constexpr (KP == 64)
-            if (c0 + PW == HALF) syrk_trailing(A);
+        Sync::sync();
+    }
+}
+
+// Factor the KP x KP matrix whose row ri = lane % KP is in A (registers):
+// afterwards A holds row ri of L (lower, L L^T = P) and invbuf[k] = 1/L_kk.
+// `pbuf` is KP x 12 floats of LDS scratch.
+//
+// The factorisation runs in panels of 8 columns (chol_panel).  Entries right
+// of the diagonal are updated too but never read, so the loops need no lane
+// masks.  An unusable pivot gives a NaN, infinite or zero 1/sqrt, caught by
+// chol_pivots_fail.
+//
+// KP = 64: the panels' updates reach only the next panel of their 16-column
+// block on the vector units; everything further right is a matrix-core
+// product: columns 16..31 of all rows from columns 0..15 (gemm_cols16_31),
+// the trailing 32 x 32 block A22 -= L21 L21^T from columns 0..31, and
+// columns 48..63 of rows 32..63 from columns 32..47 (syrk_lower_rows).
+// That leaves 480 multiply-add instructions per lane on the vector units (224
+// inside the panels, 256 for the next panel), against 992 when only A22 was
+// a matrix-core product.
+template <int KP, class Sync = BlockSync>
+__device__ __forceinline__ void chol_factor(float (&A)[KP], float *invbuf, float *pbuf)
+{
+    if constexpr (KP == 64) {
+        chol_panel<KP, Sync>(A, invbuf, pbuf, 0, 16);
+        chol_panel<KP, Sync>(A, invbuf, pbuf, 8, 16);
+        gemm_cols16_31(A);
+        chol_panel<KP, Sync>(A, invbuf, pbuf, 16, 32);
+        chol_panel<KP, Sync>(A, invbuf, pbuf, 24, 32);
+        syrk_lower_rows<0, 32, 0>(A);
+        chol_panel<KP, Sync>(A, invbuf, pbuf, 32, 48);
+        chol_panel<KP, Sync>(A, invbuf, pbuf, 40, 48);
+        syrk_lower_rows<32, 16, 2>(A);
+        chol_panel<KP, Sync>(A, invbuf, pbuf, 48, 64);
+        chol_panel<KP, Sync>(A, invbuf, pbuf, 56, 64);
+    } else {
+#pragma unroll
+        for (int c0 = 0; c0 < KP; c0 += 8) chol_panel<KP, Sync>(A, invbuf, pbuf, c0, KP);
     }
 }
 
