@@ -17,9 +17,10 @@
 //    three, two and two tiles on the four wavefronts; the right-hand side on
 //    v_dot2c_f32_bf16 (threads 0..127, one feature each);
 //  * wavefront 0 factors P11 with the 64-wide row-per-lane Cholesky and does
-//    the forward solve of block 1; wavefront 1 solves for L21 (a row per
-//    lane) and forms L21 L21^T on FP32 matrix cores; wavefront 2 factors the
-//    updated P22 and solves block 2; wavefront 0 finishes block 1.
+//    the forward solve of block 1, while wavefront 1 solves for L21 (a row
+//    per lane) one 8-column panel behind it; wavefronts 1..3 form one tile
+//    each of L21 L21^T on FP32 matrix cores; wavefront 2 factors the updated
+//    P22 and solves block 2; wavefront 0 finishes block 1.
 //  * a row whose pivot is not finite or not above 64 K 2^-24 max_k P_kk is
 //    not written; it is appended to the FP64 recompute list.
 #include "common.hpp"
@@ -225,77 +226,102 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     __syncthreads();
     const float tau = 64.0f * (float)K * 0x1.0p-24f * fmaxf(red[0], red[1]);
 
-    // ---------------- block 1: L11, y1 (wavefront 0); P21 rows (wavefront 1) ----------------
+    // ---------------- block 1: L11 (wavefront 0) and L21 (wavefront 1), panel by panel ----------------
+    // Wavefront 0 factors P11 with the 64-wide row-per-lane Cholesky in eight
+    // steps of 8 columns; after step p it publishes the panel's columns of
+    // L11 into the packed triangle (over P11, lower part only: entries right
+    // of a row's diagonal would land in the next rows' slots).  Wavefront 1
+    // keeps row r of P21 in registers and, one step behind, solves the same 8
+    // columns of L21 = P21 L11^{-T} right-looking: x_k = a_k / L11_kk, then
+    // a_j -= x_k L11_jk for the later columns.  Every thread passes the same
+    // barriers; only the work between them differs by wavefront.
     float A[H2];
     if (wave == 0) {
 #pragma unroll
         for (int c = 0; c < H2; ++c) A[c] = P[rowoff(lane) + c];
-        WaveSync::sync();
-        chol_factor<H2, WaveSync>(A, inv11, pb);
-        const float iv = inv11[lane];
-        const bool f0 = chol_pivots_fail(iv, lane, K < H2 ? K : H2, tau);
-        if (lane == 0) fails[0] = f0 ? 1 : 0;
-        forward_sub<H2, WaveSync>(A, iv, bvec[lane], y1);
-        store_rows<H2>(A, P);  // L11 over P11
     } else if (wave == 1) {
 #pragma unroll
         for (int c = 0; c < H2; ++c) A[c] = P[rowoff(H2 + lane) + c];
     }
+    auto publish = [&](int c0) {
+#pragma unroll
+        for (int c = c0; c < c0 + 8; ++c)
+            if (c <= lane) P[rowoff(lane) + c] = A[c];
+    };
+    auto trsm_panel = [&](int c0) {
+#pragma unroll
+        for (int k = c0; k < c0 + 8; ++k) {
+            const float x = A[k] * inv11[k];
+            A[k] = x;
+#pragma unroll
+            for (int j = k + 1; j < c0 + 8; ++j) A[j] = fmaf(-x, P[rowoff(j) + k], A[j]);
+        }
+#pragma unroll
+        for (int j = c0 + 8; j < H2; ++j) {
+            const float *lj = P + rowoff(j) + c0;
+            float t = A[j];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t = fmaf(-A[c0 + k], lj[k], t);
+            A[j] = t;
+        }
+    };
+#define BLOCK1_STEP(Q)                                                   \
+    if (wave == 0) {                                                     \
+        chol64_step<Q, WaveSync>(A, inv11, pb);                          \
+        publish(8 * (Q));                                                \
+    }                                                                    \
+    __syncthreads();                                                     \
+    if (wave == 1) trsm_panel(8 * (Q));
+    BLOCK1_STEP(0)
+    BLOCK1_STEP(1)
+    BLOCK1_STEP(2)
+    BLOCK1_STEP(3)
+    BLOCK1_STEP(4)
+    BLOCK1_STEP(5)
+    BLOCK1_STEP(6)
+    BLOCK1_STEP(7)
+#undef BLOCK1_STEP
+    if (wave == 0) {
+        const float iv = inv11[lane];
+        const bool f0 = chol_pivots_fail(iv, lane, K < H2 ? K : H2, tau);
+        if (lane == 0) fails[0] = f0 ? 1 : 0;
+        forward_sub<H2, WaveSync>(A, iv, bvec[lane], y1);
+    }
     __syncthreads();
 
-    // ---------------- L21, b2 - L21 y1, P22 - L21 L21^T (wavefront 1) ----------------
+    // ---------------- b2 - L21 y1 and L21 into LDS (wavefront 1) ----------------
     if (wave == 1) {
-        // row r of L21 solves x L11^T = P21 row r: x_k = (p_k - sum_{m<k} L11_km x_m) / L11_kk
-#pragma unroll
-        for (int k = 0; k < H2; ++k) {
-            const float *lk = P + rowoff(k);
-            float s0 = A[k], s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-#pragma unroll
-            for (int m = 0; m + 3 < k; m += 4) {
-                s0 = fmaf(-lk[m], A[m], s0);
-                s1 = fmaf(-lk[m + 1], A[m + 1], s1);
-                s2 = fmaf(-lk[m + 2], A[m + 2], s2);
-                s3 = fmaf(-lk[m + 3], A[m + 3], s3);
-            }
-#pragma unroll
-            for (int m = k & ~3; m < k; ++m) s0 = fmaf(-lk[m], A[m], s0);
-            A[k] = ((s0 + s1) + (s2 + s3)) * inv11[k];
-        }
-        // b2 - L21 y1
         float t = bvec[H2 + lane];
 #pragma unroll
         for (int k = 0; k < H2; ++k) t = fmaf(-A[k], y1[k], t);
         b2[lane] = t;
-        // L21 over P21 (read again by the block-1 back substitution)
+        // L21 over P21 (the operands of L21 L21^T, then the block-1 back substitution)
 #pragma unroll
         for (int c = 0; c < H2; ++c) P[rowoff(H2 + lane) + c] = A[c];
-        // C = L21 L21^T in three 32 x 32 tiles (rows 0-31 "lo", 32-63 "hi" of
-        // L21), 32 rank-2 steps of v_mfma_f32_32x32x2_f32 each.  One
-        // permlane32 swap of columns 2kk and 2kk+1 gives both operands: the
-        // first result has the lo rows' two columns in the two lane halves,
-        // the second the hi rows'.
-        floatx16 c00 = {}, c10 = {}, c11 = {};
+    }
+    __syncthreads();
+
+    // ---------------- P22 -= L21 L21^T: one 32 x 32 tile per wavefront 1..3 ----------------
+    // Tile (a, b) of C = L21 L21^T (a, b in {0, 1}: rows 0-31 / 32-63 of L21)
+    // in 32 rank-2 steps of v_mfma_f32_32x32x2_f32; operand lane l holds
+    // L21[32 a + l % 32][2 kk + l / 32], read from LDS.  Result element
+    // v = 4j + i of lane l is C[32 a + 8j + 4(l / 32) + i][32 b + l % 32].
+    if (wave >= 1) {
+        const int ta = wave == 1 ? 0 : 1, tb = wave == 3 ? 1 : 0;
+        const float *ra = P + rowoff(H2 + 32 * ta + (lane & 31)) + (lane >> 5);
+        const float *rb = P + rowoff(H2 + 32 * tb + (lane & 31)) + (lane >> 5);
+        floatx16 c = {};
 #pragma unroll
         for (int kk = 0; kk < H2 / 2; ++kk) {
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[2 * kk]), __float_as_uint(A[2 * kk + 1]),
-                                                             false, false);
-            const float xlo = __uint_as_float(sw[0]), xhi = __uint_as_float(sw[1]);
-            c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(xlo, xlo, c00, 0, 0, 0);
-            c10 = __builtin_amdgcn_mfma_f32_32x32x2f32(xhi, xlo, c10, 0, 0, 0);
-            c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(xhi, xhi, c11, 0, 0, 0);
+            const float xa = ra[2 * kk], xb = rb[2 * kk];
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xb, c, 0, 0, 0);
         }
-        // result element v = 4j + i of lane l is C[8j + 4(l / 32) + i][l % 32]
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int m = 8 * j + 4 * (lane >> 5) + i, n = lane & 31;
-                const int e00 = rowoff(H2 + m) + H2 + n;
-                const int e10 = rowoff(H2 + 32 + m) + H2 + n;
-                const int e11 = rowoff(H2 + 32 + m) + H2 + 32 + n;
-                if (n <= m) P[e00] -= c00[4 * j + i];
-                P[e10] -= c10[4 * j + i];
-                if (n <= m) P[e11] -= c11[4 * j + i];
+                const int m = 32 * ta + 8 * j + 4 * (lane >> 5) + i, n = 32 * tb + (lane & 31);
+                if (n <= m) P[rowoff(H2 + m) + H2 + n] -= c[4 * j + i];
             }
     }
     __syncthreads();

@@ -354,33 +354,38 @@ __device__ __forceinline__ void gemm_cols16_31(float *A)
 // Columns c0..c0+7 of the matrix whose row ri = lane % KP is in A: column k
 // is scaled by 1/sqrt(P_kk) (lane k thereby holds L_kk, invbuf[k] = 1/L_kk)
 // and the later panel columns are updated with values read across lanes with
-// readlane; then, when jend > c0 + 8, every lane publishes its 8 panel
-// entries through LDS (`pbuf`) and applies the rank-8 update to its columns
-// c0 + 8 .. jend - 1.
-template <int KP, class Sync>
-__device__ __forceinline__ void chol_panel(float (&A)[KP], float *invbuf, float *pbuf, int c0, int jend)
+// readlane.  Afterwards lane ri holds L[ri][c0..c0+7] (for ri >= c0).
+template <int KP>
+__device__ __forceinline__ void chol_inpanel(float (&A)[KP], float *invbuf, int c0)
 {
-    constexpr int PW = 8;
-    // pbuf rows are 12 floats apart, so 16 consecutive lanes cover all 64
-    // LDS banks with their 16-byte writes
-    constexpr int PS = 12;
-    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int k = c0; k < c0 + PW; ++k) {
+    for (int k = c0; k < c0 + 8; ++k) {
         const float inv = __builtin_amdgcn_rsqf(readlane_f(A[k], k));
         A[k] *= inv;
         invbuf[k] = inv;
 #pragma unroll
-        for (int j = k + 1; j < c0 + PW; ++j) A[j] = fmaf(-A[k], readlane_f(A[k], j), A[j]);
+        for (int j = k + 1; j < c0 + 8; ++j) A[j] = fmaf(-A[k], readlane_f(A[k], j), A[j]);
     }
-    if (c0 + PW < jend) {
+}
+
+// The rank-8 update of columns c0 + 8 .. jend - 1 by the factored panel
+// c0..c0+7: every lane publishes its 8 panel entries through LDS (`pbuf`)
+// and updates its own row.
+template <int KP, class Sync>
+__device__ __forceinline__ void chol_next(float (&A)[KP], float *pbuf, int c0, int jend)
+{
+    // pbuf rows are 12 floats apart, so 16 consecutive lanes cover all 64
+    // LDS banks with their 16-byte writes
+    constexpr int PS = 12;
+    const int lane = threadIdx.x & 63;
+    if (c0 + 8 < jend) {
         if (lane < KP) {
             *(float4 *)(pbuf + lane * PS) = make_float4(A[c0], A[c0 + 1], A[c0 + 2], A[c0 + 3]);
             *(float4 *)(pbuf + lane * PS + 4) = make_float4(A[c0 + 4], A[c0 + 5], A[c0 + 6], A[c0 + 7]);
         }
         Sync::sync();
 #pragma unroll
-        for (int j = c0 + PW; j < jend; ++j) {
+        for (int j = c0 + 8; j < jend; ++j) {
             const float4 p0 = *(const float4 *)(pbuf + j * PS);
             const float4 p1 = *(const float4 *)(pbuf + j * PS + 4);
             float t = A[j];
@@ -396,6 +401,26 @@ __device__ __forceinline__ void chol_panel(float (&A)[KP], float *invbuf, float 
         }
         Sync::sync();
     }
+}
+
+template <int KP, class Sync>
+__device__ __forceinline__ void chol_panel(float (&A)[KP], float *invbuf, float *pbuf, int c0, int jend)
+{
+    chol_inpanel<KP>(A, invbuf, c0);
+    chol_next<KP, Sync>(A, pbuf, c0, jend);
+}
+
+// Step P (0..7) of the KP = 64 factorisation below: what precedes panel P's
+// columns (the updates by the earlier panels that are still pending) and the
+// panel itself.  After step P, lane ri holds its final L[ri][8P..8P+7].
+template <int P, class Sync>
+__device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf, float *pbuf)
+{
+    if constexpr (P == 1 || P == 3 || P == 5 || P == 7) chol_next<64, Sync>(A, pbuf, 8 * (P - 1), 8 * (P + 1));
+    if constexpr (P == 2) gemm_cols16_31(A);
+    if constexpr (P == 4) syrk_lower_rows<0, 32, 0>(A);
+    if constexpr (P == 6) syrk_lower_rows<32, 16, 2>(A);
+    chol_inpanel<64>(A, invbuf, 8 * P);
 }
 
 // Factor the KP x KP matrix whose row ri = lane % KP is in A (registers):
@@ -419,17 +444,14 @@ template <int KP, class Sync = BlockSync>
 __device__ __forceinline__ void chol_factor(float (&A)[KP], float *invbuf, float *pbuf)
 {
     if constexpr (KP == 64) {
-        chol_panel<KP, Sync>(A, invbuf, pbuf, 0, 16);
-        chol_panel<KP, Sync>(A, invbuf, pbuf, 8, 16);
-        gemm_cols16_31(A);
-        chol_panel<KP, Sync>(A, invbuf, pbuf, 16, 32);
-        chol_panel<KP, Sync>(A, invbuf, pbuf, 24, 32);
-        syrk_lower_rows<0, 32, 0>(A);
-        chol_panel<KP, Sync>(A, invbuf, pbuf, 32, 48);
-        chol_panel<KP, Sync>(A, invbuf, pbuf, 40, 48);
-        syrk_lower_rows<32, 16, 2>(A);
-        chol_panel<KP, Sync>(A, invbuf, pbuf, 48, 64);
-        chol_panel<KP, Sync>(A, invbuf, pbuf, 56, 64);
+        chol64_step<0, Sync>(A, invbuf, pbuf);
+        chol64_step<1, Sync>(A, invbuf, pbuf);
+        chol64_step<2, Sync>(A, invbuf, pbuf);
+        chol64_step<3, Sync>(A, invbuf, pbuf);
+        chol64_step<4, Sync>(A, invbuf, pbuf);
+        chol64_step<5, Sync>(A, invbuf, pbuf);
+        chol64_step<6, Sync>(A, invbuf, pbuf);
+        chol64_step<7, Sync>(A, invbuf, pbuf);
     } else {
 #pragma unroll
         for (int c0 = 0; c0 < KP; c0 += 8) chol_panel<KP, Sync>(A, invbuf, pbuf, c0, KP);
