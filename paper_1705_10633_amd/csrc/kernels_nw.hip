@@ -210,6 +210,170 @@ __global__ __launch_bounds__(NW_THREADS) void nw_kernel(const double *sums, int6
     if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
 }
 
+// ---------------------------------------------------------------------------
+// 64 < K <= 128: both sides in one launch, one 512-thread workgroup per side,
+// every matrix in LDS as a packed lower triangle (row k at k (k + 1) / 2):
+//  * PL holds P (lower part), then row by row R^T: the factorisation from the
+//    last pivot computes column k of R, R_ik = P_ki / R_kk (i < k), into row
+//    k of PL in place and then removes R_k R_k^T from the leading block;
+//  * TL holds A (Bartlett factor, written straight from the draws) and then
+//    T, the solution of R^T T = A (R_mi with m < i is PL(i, m));
+//  * Lambda = T T^T goes to global memory, Lambda mu = T (T^T mu) and the mean
+//    solve T^T d = z / sqrt(beta*) read TL.
+// Two packed 128 x 128 triangles and the vectors take 139 KB of LDS.
+// ---------------------------------------------------------------------------
+constexpr int NWP_THREADS = 512;
+constexpr int NWP_MAXK = 128;
+
+__host__ __device__ constexpr size_t nw_packed_lds_doubles(int K)
+{
+    return (size_t)K * (K + 1) + 7 * (size_t)K;
+}
+
+__device__ __forceinline__ int ptri(int r, int c) { return r * (r + 1) / 2 + c; }
+
+__global__ __launch_bounds__(NWP_THREADS) void nw_packed_kernel(NwSide side0, NwSide side1, int K,
+                                                                const double *mu0, double beta0, double nu0,
+                                                                const double *W0inv, DevState *state)
+{
+    extern __shared__ double lds[];
+    __shared__ int s_flag;
+    const NwSide sd = blockIdx.x == 0 ? side0 : side1;
+    const double *sums = sd.sums;
+    const int tid = threadIdx.x;
+    const int KT = K * (K + 1) / 2;
+    double *PL = lds;             // P, then R^T (packed lower)
+    double *TL = PL + KT;         // A, then T (packed lower)
+    double *xbar = TL + KT;       // K
+    double *rd = xbar + K;        // K: diagonal of R
+    double *chi2 = rd + K;        // K
+    double *zm = chi2 + K;        // K
+    double *dvec = zm + K;        // K
+    double *dout = dvec + K;      // K
+    double *tv = dout + K;        // K: T^T mu
+    const double dn = (double)sd.n;
+    const double bstar = beta0 + dn, nstar = nu0 + dn;
+
+    if (tid == 0) s_flag = 0;
+    // draws: chi^2 and mean normals into vectors, Bartlett normals straight into TL
+    if (sd.draws.tape_nw) {
+        for (int k = tid; k < K; k += NWP_THREADS) chi2[k] = sd.draws.tape_nw[k];
+        for (int q = tid; q < K; q += NWP_THREADS) zm[q] = sd.draws.tape_nw[K + K * (K - 1) / 2 + q];
+    } else {
+        const uint32_t h = half_sweep_index(sd.draws);
+        for (int k = tid; k < K; k += NWP_THREADS)
+            chi2[k] = 2.0 * gamma_mt(sd.draws.seed, h, (uint32_t)k, 0.5 * (nstar - (double)k));
+        for (int q = tid; q < K; q += NWP_THREADS) zm[q] = stream_normal_f64(sd.draws.seed, h, 2u, (uint32_t)q);
+    }
+    for (int a = tid; a < K; a += NWP_THREADS) xbar[a] = sd.n > 0 ? sums[a] / dn : 0.0;
+    __syncthreads();
+    // A below the diagonal: Bartlett normal q = i (i - 1) / 2 + c for (i, c), c < i
+    for (int e = tid; e < KT; e += NWP_THREADS) {
+        int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+        while (ptri(i, 0) > e) --i;
+        while (ptri(i + 1, 0) <= e) ++i;
+        const int c = e - ptri(i, 0);
+        double v;
+        if (c == i) {
+            v = sqrt(chi2[c]);
+        } else {
+            const int q = i * (i - 1) / 2 + c;
+            v = sd.draws.tape_nw ? sd.draws.tape_nw[K + q] : stream_normal_f64(sd.draws.seed, half_sweep_index(sd.draws), 1u, (uint32_t)q);
+        }
+        TL[e] = v;
+        // P = W0^{-1} + S + coef (xbar - mu0)(xbar - mu0)^T, lower part
+        const double coef = beta0 * dn / bstar;
+        const double S = sums[K + e] - dn * xbar[i] * xbar[c];
+        PL[e] = W0inv[i * K + c] + S + coef * (xbar[i] - mu0[i]) * (xbar[c] - mu0[c]);
+    }
+    // P = R R^T from the last pivot up
+    for (int k = K - 1; k >= 0; --k) {
+        __syncthreads();
+        double akk = PL[ptri(k, k)];
+        if (!(akk > 0.0) || !isfinite(akk)) {
+            if (tid == 0) s_flag = 1;
+            akk = 1.0;
+        }
+        const double rkk = sqrt(akk), inv = 1.0 / rkk;
+        __syncthreads();
+        if (tid == 0) {
+            rd[k] = rkk;
+            PL[ptri(k, k)] = rkk;
+        }
+        for (int i = tid; i < k; i += NWP_THREADS) PL[ptri(k, i)] *= inv;
+        __syncthreads();
+        // leading block: PL(ii, jj) -= R_ii,k R_jj,k for jj <= ii < k
+        const double *rk = PL + ptri(k, 0);
+        for (int e = tid; e < ptri(k, 0); e += NWP_THREADS) {
+            int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+            while (ptri(ii, 0) > e) --ii;
+            while (ptri(ii + 1, 0) <= e) ++ii;
+            const int jj = e - ptri(ii, 0);
+            PL[e] = fma(-rk[ii], rk[jj], PL[e]);
+        }
+    }
+    __syncthreads();
+    // R^T T = A, right-looking: step m fixes row m of T and removes it from
+    // the rows below (TL(i, c) -= R_mi T_mc for i > m, c <= m)
+    for (int m = 0; m < K; ++m) {
+        const double irm = 1.0 / rd[m];
+        const int rows = K - 1 - m, cols = m + 1;
+        for (int e = tid; e < rows * cols; e += NWP_THREADS) {
+            const int ii = e / cols, c = e - ii * cols;
+            const int i = m + 1 + ii;
+            TL[ptri(i, c)] = fma(-PL[ptri(i, m)], TL[ptri(m, c)] * irm, TL[ptri(i, c)]);
+        }
+        __syncthreads();
+        for (int c = tid; c <= m; c += NWP_THREADS) TL[ptri(m, c)] *= irm;
+        __syncthreads();
+    }
+    // Lambda = T T^T (T(a, m) = 0 for m > a), entries (a, c) with a >= c and their mirror
+    for (int e = tid; e < KT; e += NWP_THREADS) {
+        int a = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+        while (ptri(a, 0) > e) --a;
+        while (ptri(a + 1, 0) <= e) ++a;
+        const int c = e - ptri(a, 0);
+        const double *ta = TL + ptri(a, 0), *tc = TL + ptri(c, 0);
+        double acc = 0.0;
+        for (int m = 0; m <= c; ++m) acc = fma(ta[m], tc[m], acc);
+        sd.hyp.Lambda[a * K + c] = acc;
+        sd.hyp.Lambda[c * K + a] = acc;
+        sd.hyp.Lambda_f[a * K + c] = (float)acc;
+        sd.hyp.Lambda_f[c * K + a] = (float)acc;
+    }
+    // mean: T^T d = z / sqrt(beta*), column-oriented backward substitution
+    const double isb = 1.0 / sqrt(bstar);
+    for (int a = tid; a < K; a += NWP_THREADS) dvec[a] = zm[a] * isb;
+    for (int k = K - 1; k >= 0; --k) {
+        __syncthreads();
+        const double dk = dvec[k] / TL[ptri(k, k)];
+        __syncthreads();
+        if (tid == 0) dout[k] = dk;
+        for (int i = tid; i < k; i += NWP_THREADS) dvec[i] = fma(-TL[ptri(k, i)], dk, dvec[i]);
+    }
+    __syncthreads();
+    for (int a = tid; a < K; a += NWP_THREADS) {
+        const double mus = (beta0 * mu0[a] + dn * xbar[a]) / bstar;
+        sd.hyp.mu[a] = mus + dout[a];
+        dvec[a] = mus + dout[a];
+    }
+    __syncthreads();
+    // Lambda mu = T (T^T mu)
+    for (int m = tid; m < K; m += NWP_THREADS) {
+        double v = 0.0;
+        for (int a = m; a < K; ++a) v = fma(TL[ptri(a, m)], dvec[a], v);
+        tv[m] = v;
+    }
+    __syncthreads();
+    for (int a = tid; a < K; a += NWP_THREADS) {
+        double v = 0.0;
+        for (int m = 0; m <= a; ++m) v = fma(TL[ptri(a, m)], tv[m], v);
+        sd.hyp.Lmu[a] = v;
+        sd.hyp.Lmu_f[a] = (float)v;
+    }
+    if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
+}
+
 constexpr int NWK = 64;       // padded size (K <= 64)
 constexpr int NPW = 8;        // panel width
 
@@ -500,8 +664,11 @@ __global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, in
 
 hipError_t prepare_nw()
 {
-    return hipFuncSetAttribute((const void *)nw_compact_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)nw_compact_lds_bytes());
+    hipError_t e = hipFuncSetAttribute((const void *)nw_compact_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)nw_compact_lds_bytes());
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)nw_packed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(sizeof(double) * nw_packed_lds_doubles(NWP_MAXK)));
 }
 
 hipError_t launch_lambda_tri(HyperDev hyp, int K, int KP, hipStream_t s)
@@ -532,6 +699,11 @@ hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double bet
     if (K <= NWK) {
         hipLaunchKernelGGL(nw_compact_kernel, dim3(2), dim3(256), nw_compact_lds_bytes(), s, sides[0], sides[1],
                            K, mu0, beta0, nu0, W0inv, state);
+        return hipGetLastError();
+    }
+    if (K <= NWP_MAXK) {
+        hipLaunchKernelGGL(nw_packed_kernel, dim3(2), dim3(NWP_THREADS), sizeof(double) * nw_packed_lds_doubles(K), s,
+                           sides[0], sides[1], K, mu0, beta0, nu0, W0inv, state);
         return hipGetLastError();
     }
     for (int sd = 0; sd < 2; ++sd) {
