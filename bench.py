@@ -44,18 +44,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def rows_kernel_flops(row_counts, col_counts, K):
-    """Algorithmic work of the row-update kernel over one sweep (both halves).
+def rows_kernel_flops(rows, nnz, K):
+    """Algorithmic work of `rows` row updates with `nnz` ratings in all.
 
-    VALU (FP32): Cholesky K^3/3, two triangular solves 2 K^2, forming P
-    K(K+1), right-hand side 2 nnz K.  Matrix cores (BF16): the symmetric Gram
-    nnz K(K+1).
+    FP32 (vector units or FP32 matrix cores): Cholesky K^3/3, two triangular
+    solves 2 K^2, forming P K(K+1), right-hand side 2 nnz K.  BF16 matrix
+    cores: the symmetric Gram nnz K(K+1).
     """
-    rows = row_counts.size + col_counts.size
-    nnz = int(row_counts.sum() + col_counts.sum())
     valu = rows * (K ** 3 / 3.0 + 2.0 * K * K + K * (K + 1)) + 2.0 * nnz * K
     mfma = float(nnz) * K * (K + 1)
-    return valu, mfma, rows, nnz
+    return valu, mfma
+
+
+def full_kernel_rows(counts, rank1_rows):
+    """(rows, ratings) of one side that the full row kernel handles (the
+    one-wavefront launch, with the heavy rows' pieces and their combine
+    launch): every row but the rank-one tail of the count order."""
+    c = np.sort(np.asarray(counts, np.int64))[::-1]
+    keep = c[:c.size - int(rank1_rows)]
+    return int(keep.size), int(keep.sum())
 
 
 # The workloads of the paper's benchmarks (synthetic stand-ins); the metric
@@ -68,8 +75,8 @@ WORKLOADS = {
                    text="ChEMBL-shaped synthetic: 483,500 x 5,775, 1,023,952 ratings (97% of rows with one), K=32, "
                         "FP32 gathers/Gram/Cholesky + FP64 hyper step, HIP-graph sweep"),
     "netflix": dict(gen="netflix_like", precision="bf16",
-                    text="Netflix-shaped synthetic: 480,189 x 17,770, 100M ratings, K=128, FP32 storage with FP64 "
-                         "row arithmetic (the mixed kernels cover K <= 64) + FP64 hyper step, HIP-graph sweep"),
+                    text="Netflix-shaped synthetic: 480,189 x 17,770, 100M ratings, K=128, BF16 gathers/Gram on "
+                         "matrix cores + FP32 Cholesky (four wavefronts per row) + FP64 hyper step, HIP-graph sweep"),
 }
 
 
@@ -230,7 +237,7 @@ def main():
         f"nnz={prob.R.nnz} K={K} ({prob.note})")
 
     R32 = DeviceRatings(prob.R, val_dtype="float32")
-    shape, tune_table = (json.loads(args.shape) if args.shape else {}), None
+    shape, tune_table, tune_fits = (json.loads(args.shape) if args.shape else {}), None, None
     if args.autotune:
         from paper_1705_10633_amd import autotune
         t0 = time.perf_counter()
@@ -238,6 +245,10 @@ def main():
             R32, K, prob.U0.astype(np.float32), prob.V0.astype(np.float32),
             [prob.R.row_counts(), prob.R.col_counts()], precision=prec, sweeps=args.steps, warmup=3,
             alpha=prob.alpha, beta0=prob.beta0, nu0=prob.nu0, mean_rating=prob.mean_rating, seed=2024)
+        tune_fits = autotune.variant_fits()
+        for f in tune_fits:
+            log(f"[bench] autotune variant {f['variant']}: {f['ms_per_sweep']:.3f} ms/sweep, row cost fit "
+                f"a = {f['a_us_per_row']:.4g} us/row + b = {f['b_us_per_rating']:.4g} us/rating per launch")
         for c, ms in tune_table:
             log(f"[bench] autotune {ms:8.3f} ms/sweep  {c}")
         log(f"[bench] autotune: {len(tune_table)} shapes in {time.perf_counter() - t0:.1f} s, "
@@ -255,7 +266,8 @@ def main():
         print(json.dumps({"metric": f"Gibbs rows sampled/sec at K={K}", "value": value, "ms_per_step": ms_wall,
                           "workload": args.workload, "launch_shape": shape,
                           "autotune": None if tune_table is None else
-                          [{"shape": c, "ms_per_sweep": ms} for c, ms in tune_table]}))
+                          {"timed": [{"shape": c, "ms_per_sweep": ms} for c, ms in tune_table],
+                           "kernel_variant_fits": tune_fits}}))
         return
 
     # four more runs of the same number of sweeps, for the spread between runs
@@ -276,23 +288,52 @@ def main():
     for k, (ms, n) in tm.items():
         log(f"[bench]   {k:15s} {ms / max(n, 1) * 1e3:9.1f} us/launch x {n}")
     rc, cc = prob.R.row_counts(), prob.R.col_counts()
-    valu, mfma, _, nnz = rows_kernel_flops(rc, cc, K)
-    t_rows = (tm["rows_users"][0] + tm["rows_movies"][0]) / args.steps  # ms per sweep, both launches
-    launches = 2
+    # The dominant kernel: the full row kernel (one wavefront per row at K <= 64,
+    # four at K = 128), its users' and movies' launches and, where heavy rows are
+    # cut into pieces, their combine launch; the rank-one tail runs in kernels of
+    # its own and is neither timed nor counted here.
+    per_launch = {}
+    valu = mfma = 0.0
+    t_rows = 0.0
+    launches = 0
+    for side, cls, counts in ((0, "rows_users", rc), (1, "rows_movies", cc)):
+        rows, nnz = full_kernel_rows(counts, info["rank1_rows"][side])
+        v, m = rows_kernel_flops(rows, nnz, K)
+        ms, n = tm[cls]
+        us = ms / max(n, 1) * 1e3
+        per_launch[cls] = {"rows": rows, "ratings": nnz, "avg_us": us, "fp32_flop": v, "bf16_mfma_flop": m,
+                           "fp32_TFLOPs": v / (us * 1e-6) / 1e12 if us > 0 else None,
+                           "fp32_frac": v / (us * 1e-6) / 1e12 / MI355X["fp32_TFLOPs"] if us > 0 else None,
+                           "bf16_mfma_frac": m / (us * 1e-6) / 1e12 / MI355X["bf16_TFLOPs"] if us > 0 else None}
+        valu += v
+        mfma += m
+        t_rows += ms / args.steps
+        launches += n / args.steps
+    if tm["rows_heavy"][1]:
+        t_rows += tm["rows_heavy"][0] / args.steps
+        launches += tm["rows_heavy"][1] / args.steps
+        per_launch["rows_heavy"] = {"avg_us": tm["rows_heavy"][0] / tm["rows_heavy"][1] * 1e3,
+                                    "note": "factorisation of the heavy rows whose Gram ran in pieces"}
     avg_launch_ms = t_rows / launches
     achieved = (valu / launches) / (avg_launch_ms * 1e-3) / 1e12
     mfma_achieved = (mfma / launches) / (avg_launch_ms * 1e-3) / 1e12
     traffic, traffic_note = measured_traffic() if args.workload == "movielens" else (
         None, "counter summary is for the MovieLens-shaped row kernel only")
-    peak = MI355X["fp32_TFLOPs"] if K <= 64 else MI355X["fp64_TFLOPs"]  # K > 64: FP64 row arithmetic
+    peak = MI355X["fp32_TFLOPs"]
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic}
-    kname = f"rows_mixed_kernel<{32 if K <= 32 else 64},{prec}>" if K <= 64 else "rows_f64_kernel<float,float>"
+    if K <= 64:
+        kname = f"rows_mixed_kernel<{32 if K <= 32 else 64},{prec}>"
+    else:
+        kname = "rows_mixed128_kernel"
     detail = {"kernel": kname, "avg_launch_us": avg_launch_ms * 1e3,
               "valu_flop_per_sweep": valu, "mfma_bf16_flop_per_sweep": mfma,
               "mfma_bf16_achieved_TFLOPs": mfma_achieved,
               "mfma_bf16_frac": mfma_achieved / MI355X["bf16_TFLOPs"],
+              "fp32_frac_of_unpacked_peak": achieved / (MI355X["fp32_TFLOPs"] / 2),
+              "per_launch": per_launch,
               "per_kernel_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in tm.items()},
+              "launch_shape_info": {k: info[k] for k in ("rank1_rows", "heavy_rows", "pieces", "kernel_variant")},
               "fallback_rows": info["fallback_rows"],
               "traffic_note": traffic_note,
               "hbm_GBs_at_traffic": (traffic / (avg_launch_ms * 1e-3) / 1e9) if traffic else None}
@@ -337,7 +378,7 @@ def main():
         "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_wall, "ms_per_step_runs": runs, "ms_per_step_median_of_runs": float(np.median(runs)),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": prec if K <= 64 else "f64", "data": "synthetic",
+        "dtype": prec, "data": "synthetic",
         "config": {"workload": wl["text"],
                    "M": prob.M, "N": prob.N, "nnz": prob.R.nnz, "K": K,
                    "rows_per_step": rows_per_sweep, "n_test": int(prob.test_rows.size)},
@@ -350,9 +391,8 @@ def main():
         "launch_shape": shape,
     }
     if tune_table is not None:
-        # with a non-built-in shape some rows run in the rank-one or piece launches, which the
-        # roofline's two row launches then no longer hold
-        out["autotune"] = [{"shape": c, "ms_per_sweep": ms} for c, ms in tune_table]
+        out["autotune"] = {"timed": [{"shape": c, "ms_per_sweep": ms} for c, ms in tune_table],
+                           "kernel_variant_fits": tune_fits}
     print(json.dumps(out))
 
 

@@ -104,6 +104,13 @@ typedef struct {
  *   rank1_split        1: always use the rank-one launch when such rows exist,
  *                      -1: never, 0: only when they are >= 16384 rows or
  *                      >= 1/16 of the side
+ *   kernel_variant     code variant of the one-wavefront row kernel at
+ *                      32 < K <= 64 (the same arithmetic, other rounding order
+ *                      or register budget): 0 or 1: the Cholesky's trailing
+ *                      updates beyond the next panel on FP32 matrix cores,
+ *                      4 wavefronts per SIMD; 2: those updates on the vector
+ *                      units within each 32-column half; 3: as 1, register
+ *                      allocation held to 3 wavefronts per SIMD
  * Out-of-range fields make bpmf_workspace_size and bpmf_init return
  * BPMF_E_INVALID. */
 typedef struct {
@@ -112,6 +119,7 @@ typedef struct {
     int32_t heavy_split;
     int32_t rank1_max_ratings;
     int32_t rank1_split;
+    int32_t kernel_variant;
 } bpmf_launch_shape;
 
 /* Model and run parameters (Section 2: Gaussian rows, Normal-Wishart hyperpriors).
@@ -196,6 +204,12 @@ typedef struct {
     int64_t nonfinite_rows;/* rows whose FP64 draw was not finite since init */
     double mean_rating;
     int32_t K, precision;
+    /* how init cut each side's rows into launches (users [0], movies [1]):
+     * rows taken by the rank-one kernels, heavy rows cut into pieces and
+     * their piece count; the other rows run in the one-wavefront launch
+     * (FP32/BF16 with K <= 64; zero otherwise) */
+    int64_t rank1_rows[2], heavy_rows[2], pieces[2];
+    int32_t kernel_variant; /* resolved bpmf_launch_shape::kernel_variant (0: none applies) */
 } bpmf_info;
 
 /* Counters; synchronises `stream`. */

@@ -32,7 +32,7 @@ class Ratings(C.Structure):
 
 class LaunchShape(C.Structure):
     _fields_ = [("heavy_min_ratings", I32), ("piece_min_ratings", I32), ("heavy_split", I32),
-                ("rank1_max_ratings", I32), ("rank1_split", I32)]
+                ("rank1_max_ratings", I32), ("rank1_split", I32), ("kernel_variant", I32)]
 
 
 class Params(C.Structure):
@@ -44,7 +44,9 @@ class Params(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("sweeps_done", I64), ("fallback_rows", I64), ("nonfinite_rows", I64),
-                ("mean_rating", F64), ("K", I32), ("precision", I32)]
+                ("mean_rating", F64), ("K", I32), ("precision", I32),
+                ("rank1_rows", I64 * 2), ("heavy_rows", I64 * 2), ("pieces", I64 * 2),
+                ("kernel_variant", I32)]
 
 
 class FoldinModel(C.Structure):

@@ -99,11 +99,12 @@ static int64_t rank1_limit(int K)
 struct LaunchShape {
     int64_t heavy_min, piece_min, rank1_max;
     int heavy_split, rank1_split;
+    int variant;  // kernel variant of the K <= 64 row kernel (1..3)
 };
 
 static LaunchShape resolve_shape(const bpmf_launch_shape *sh, int K)
 {
-    LaunchShape r{heavy_min_ratings(), 512, rank1_limit(K), 0, 0};
+    LaunchShape r{heavy_min_ratings(), 512, rank1_limit(K), 0, 0, 1};
     if (!sh) return r;
     if (sh->heavy_min_ratings) r.heavy_min = sh->heavy_min_ratings;
     if (sh->piece_min_ratings) r.piece_min = sh->piece_min_ratings;
@@ -111,6 +112,7 @@ static LaunchShape resolve_shape(const bpmf_launch_shape *sh, int K)
     if (sh->rank1_max_ratings) r.rank1_max = sh->rank1_max_ratings < 0 ? -1 : sh->rank1_max_ratings;
     r.heavy_split = sh->heavy_split;
     r.rank1_split = sh->rank1_split;
+    if (sh->kernel_variant) r.variant = sh->kernel_variant;
     return r;
 }
 
@@ -186,6 +188,7 @@ struct bpmf_ctx {
     // entries of the launch table per side (pieces and rows)
     int64_t n_entries[2] = {0, 0};
     bool records = false;  // BF16 mode: the row kernels read packed rating records
+    int variant = 1;       // kernel variant of the K <= 64 row kernel
     int64_t n_test;
     const int32_t *test_rows, *test_cols;
     hipGraph_t graph = nullptr;
@@ -265,6 +268,8 @@ static bpmf_status check_params(const bpmf_ratings *R, const bpmf_params *p)
             return fail(BPMF_E_INVALID, "shape.piece_min_ratings must be 0 or >= 64");
         if (sh->heavy_split < -1 || sh->heavy_split > 1 || sh->rank1_split < -1 || sh->rank1_split > 1)
             return fail(BPMF_E_INVALID, "shape.heavy_split and shape.rank1_split must be -1, 0 or 1");
+        if (sh->kernel_variant < 0 || sh->kernel_variant > 3)
+            return fail(BPMF_E_INVALID, "shape.kernel_variant must be 0..3");
         if (sh->rank1_max_ratings < -1 || sh->rank1_max_ratings > rank1_max_ratings())
             return fail(BPMF_E_INVALID, "shape.rank1_max_ratings must be -1, 0 or 1.." +
                                             std::to_string(rank1_max_ratings()));
@@ -452,6 +457,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
 
     const LaunchShape shape = resolve_shape(p->shape, K);
     c->records = p->precision == BPMF_BF16 && mixed_supported(K, p->precision);
+    c->variant = shape.variant;
     // row order: rating count descending, ties by index
     for (int sd = 0; sd < 2; ++sd) {
         std::vector<int32_t> ord(n[sd]);
@@ -739,13 +745,13 @@ static bpmf_status enqueue_rows(bpmf_ctx *c, int side, const DrawSrc &d, hipStre
         pc.combine = 0;
         t0 = time_begin(c, s);
         HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state, pc,
-                                 np + (n - ns - nh), s));
+                                 np + (n - ns - nh), c->variant, s));
         time_end(c, 2 + side, t0, s);
         if (nh > 0) {
             pc.combine = 1;
             t0 = time_begin(c, s);
             HIP_OK(launch_rows_mixed(a, K, c->KP, bf16 ? 1 : 0, c->alpha, c->rbar, c->hyp[side], d, fbl, c->state,
-                                     pc, nh, s));
+                                     pc, nh, c->variant, s));
             time_end(c, 8, t0, s);
         }
         if (ns > 0) {
@@ -891,6 +897,12 @@ bpmf_status bpmf_get_info(bpmf_ctx *c, bpmf_info *info, void *stream)
     info->mean_rating = c->rbar;
     info->K = c->K;
     info->precision = c->precision;
+    for (int sd = 0; sd < 2; ++sd) {
+        info->rank1_rows[sd] = c->n_small[sd];
+        info->heavy_rows[sd] = c->n_heavy[sd];
+        info->pieces[sd] = c->n_pieces[sd];
+    }
+    info->kernel_variant = (c->precision != BPMF_FP64 && c->K <= 64) ? c->variant : 0;
     return BPMF_OK;
 }
 

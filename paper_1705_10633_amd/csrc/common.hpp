@@ -171,9 +171,10 @@ struct PieceArgs {
 };
 // n_entries entries of a.rowtab (pieces have row < 0), or with pc.combine
 // n_entries heavy rows from pc.ctab.
+// variant: bpmf_launch_shape::kernel_variant resolved (1..3; KP = 64 only).
 hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double alpha,
                              double rbar, HyperDev hyp, DrawSrc draws, int32_t *fb_list,
-                             DevState *state, PieceArgs pc, int64_t n_entries, hipStream_t s);
+                             DevState *state, PieceArgs pc, int64_t n_entries, int variant, hipStream_t s);
 // Rows with at least this many ratings are cut into pieces (K <= 64).
 int heavy_min_ratings();
 // Rows in order slots [slot0, slot1), each with at most rank1_max_ratings()

@@ -29,8 +29,12 @@ namespace {
 // One wavefront per heavy row would leave a row with thousands of ratings
 // running long after the rest of the launch (the load imbalance of heavy
 // items, paper Section 3.2).
-template <int KP, bool BF16>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void rows_mixed_kernel(SideArgs a, int K, float alpha, float rbar,
+// Kernel variants (bpmf_launch_shape::kernel_variant; KP = 64 only): MT
+// selects the matrix-core trailing updates of chol_factor, W the
+// wavefronts per SIMD the register allocation is held to (W = 4: at most 128
+// VGPRs; W = 3: 168).
+template <int KP, bool BF16, bool MT = true, int W = 4>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void rows_mixed_kernel(SideArgs a, int K, float alpha, float rbar,
                                                         HyperDev hyp, DrawSrc draws,
                                                         int32_t *fb_list, DevState *state,
                                                         int side, PieceArgs pc)
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     __syncthreads();
 
     bool fail;
-    const float x = chol_solve<KP>(tri, colbuf, K, bb, z, fail);
+    const float x = chol_solve<KP, BlockSync, MT>(tri, colbuf, K, bb, z, fail);
     if (!fail) {
         float *X = (float *)a.X;
         if (lane < KP && ri < K) X[(int64_t)row * K + ri] = x;
@@ -167,20 +171,33 @@ int heavy_min_ratings() { return 2048; }
 
 hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double alpha, double rbar,
                              HyperDev hyp, DrawSrc draws, int32_t *fb_list, DevState *state,
-                             PieceArgs pc, int64_t n_entries, hipStream_t s)
+                             PieceArgs pc, int64_t n_entries, int variant, hipStream_t s)
 {
     if (n_entries <= 0) return hipSuccess;
     const dim3 grid((unsigned)n_entries), block(64);
     const float fa = (float)alpha, fr = (float)rbar;
+#define BPMF_ROWS_MIXED(...) hipLaunchKernelGGL((rows_mixed_kernel<__VA_ARGS__>), grid, block, 0, s, a, K, fa, fr, hyp, \
+                                                draws, fb_list, state, draws.side, pc)
     if (KP == 64) {
-        if (bf16) hipLaunchKernelGGL((rows_mixed_kernel<64, true>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side, pc);
-        else hipLaunchKernelGGL((rows_mixed_kernel<64, false>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side, pc);
+        // 1: matrix-core trailing updates, 4 wavefronts per SIMD (built-in);
+        // 2: vector-unit updates within each 32-column half; 3: as 1 with 3
+        // wavefronts per SIMD
+        if (bf16) {
+            if (variant == 2) BPMF_ROWS_MIXED(64, true, false, 4);
+            else if (variant == 3) BPMF_ROWS_MIXED(64, true, true, 3);
+            else BPMF_ROWS_MIXED(64, true, true, 4);
+        } else {
+            if (variant == 2) BPMF_ROWS_MIXED(64, false, false, 4);
+            else if (variant == 3) BPMF_ROWS_MIXED(64, false, true, 3);
+            else BPMF_ROWS_MIXED(64, false, true, 4);
+        }
     } else if (KP == 32) {
         if (bf16) hipLaunchKernelGGL((rows_mixed_kernel<32, true>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side, pc);
         else hipLaunchKernelGGL((rows_mixed_kernel<32, false>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side, pc);
     } else {
         return hipErrorInvalidValue;
     }
+#undef BPMF_ROWS_MIXED
     return hipGetLastError();
 }
 

@@ -440,10 +440,20 @@ __device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf, float
 // That leaves 480 multiply-add instructions per lane on the vector units (224
 // inside the panels, 256 for the next panel), against 992 when only A22 was
 // a matrix-core product.
-template <int KP, class Sync = BlockSync>
+//
+// MT = false (a launch-shape variant): KP = 64 with the panels' updates on the
+// vector units up to the end of their 32-column half, and only A22 -= L21
+// L21^T (columns 0..31 into 32..63 of rows 32..63) as a matrix-core product.
+template <int KP, class Sync = BlockSync, bool MT = true>
 __device__ __forceinline__ void chol_factor(float (&A)[KP], float *invbuf, float *pbuf)
 {
-    if constexpr (KP == 64) {
+    if constexpr (KP == 64 && !MT) {
+#pragma unroll
+        for (int c0 = 0; c0 < KP; c0 += 8) {
+            chol_panel<KP, Sync>(A, invbuf, pbuf, c0, c0 < 32 ? 32 : 64);
+            if (c0 == 24) syrk_lower_rows<0, 32, 0>(A);
+        }
+    } else if constexpr (KP == 64) {
         chol64_step<0, Sync>(A, invbuf, pbuf);
         chol64_step<1, Sync>(A, invbuf, pbuf);
         chol64_step<2, Sync>(A, invbuf, pbuf);
@@ -544,7 +554,7 @@ __device__ __forceinline__ float backward_sub(const float *tri, float invd, floa
 // across the wave) when a pivot is not finite or not above
 // 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with L; `aux` holds 3 KP floats.
 // Lane ri keeps row ri of P in registers through chol_factor.
-template <int KP, class Sync = BlockSync>
+template <int KP, class Sync = BlockSync, bool MT = true>
 __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float bb, float z,
                                             bool &fail)
 {
@@ -560,7 +570,7 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
     for (int o = 32; o >= 1; o >>= 1) dg = fmaxf(dg, __shfl_xor(dg, o));
     const float tau = 64.0f * (float)K * 0x1.0p-24f * dg;
     Sync::sync();
-    chol_factor<KP, Sync>(A, invbuf, tri);  // P is in registers: tri serves as the panel buffer
+    chol_factor<KP, Sync, MT>(A, invbuf, tri);  // P is in registers: tri serves as the panel buffer
     fail = chol_pivots_fail(invbuf[ri], ri, K, tau);
     const float invd = invbuf[ri];
     const float y = forward_sub<KP, Sync>(A, invd, bb, ybuf);

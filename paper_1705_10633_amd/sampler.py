@@ -61,18 +61,30 @@ class Sampler:
         torch = _torch()
         self.torch = torch
         self.tune_table = None
+        self.tune_cached = False
         if isinstance(shape, str):
-            # "auto": time the candidate launch shapes on this problem first and keep the
-            # fastest (only the mixed-precision kernels for K <= 64 have shapes to choose)
-            if shape != "auto":
+            # "auto": the cached shape of this problem (GPU architecture, K, precision,
+            # rating-count histogram), else time the candidates on this problem first
+            # and keep (and cache) the fastest; only the mixed-precision kernels for
+            # K <= 64 have shapes to choose
+            if shape not in ("auto", "auto-nocache"):
                 raise ValueError("shape must be None, a dict of bpmf_launch_shape fields or 'auto'")
+            use_cache = shape == "auto"
             shape = {}
             if precision != "fp64" and K <= 64:
                 from . import autotune
                 counts = [torch.diff(ratings.row_ptr).cpu().numpy(), torch.diff(ratings.col_ptr).cpu().numpy()]
-                shape, self.tune_table = autotune.tune(
-                    ratings, K, U0, V0, counts, precision=precision, alpha=alpha, beta0=beta0, nu0=nu0,
-                    mu0=mu0, W0=W0, mean_rating=mean_rating, seed=seed)
+                arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+                key = autotune.problem_key(counts, K, precision, arch)
+                cached = autotune.cache_lookup(key) if use_cache else None
+                if cached is not None:
+                    shape, self.tune_cached = cached, True
+                else:
+                    shape, self.tune_table = autotune.tune(
+                        ratings, K, U0, V0, counts, precision=precision, alpha=alpha, beta0=beta0, nu0=nu0,
+                        mu0=mu0, W0=W0, mean_rating=mean_rating, seed=seed)
+                    if use_cache:
+                        autotune.cache_store(key, shape, self.tune_table, autotune.variant_fits())
         self.R = ratings
         self.K = K
         self.precision = precision
@@ -153,7 +165,9 @@ class Sampler:
         i = _lib.Info()
         call("bpmf_get_info", self.ctx, C.byref(i), _stream(self.torch, stream))
         return {"sweeps_done": i.sweeps_done, "fallback_rows": i.fallback_rows,
-                "nonfinite_rows": i.nonfinite_rows, "mean_rating": i.mean_rating}
+                "nonfinite_rows": i.nonfinite_rows, "mean_rating": i.mean_rating,
+                "rank1_rows": tuple(i.rank1_rows), "heavy_rows": tuple(i.heavy_rows),
+                "pieces": tuple(i.pieces), "kernel_variant": i.kernel_variant}
 
     def set_timing(self, enable: bool):
         """Bracket every launch with HIP events (sweeps then run without graph replay)."""

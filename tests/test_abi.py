@@ -155,10 +155,10 @@ def test_launch_shape_fields_are_validated(lib):
     R = _ratings()
     good = [{}, {"heavy_min_ratings": 64, "piece_min_ratings": 64, "heavy_split": 1},
             {"heavy_split": -1, "rank1_max_ratings": -1}, {"rank1_max_ratings": 4, "rank1_split": 1},
-            {"rank1_split": -1}]
+            {"rank1_split": -1}, {"kernel_variant": 1}, {"kernel_variant": 2}, {"kernel_variant": 3}]
     bad = [{"heavy_min_ratings": 63}, {"heavy_min_ratings": -5}, {"piece_min_ratings": 1},
            {"heavy_split": 2}, {"rank1_split": -2}, {"rank1_max_ratings": 5},
-           {"rank1_max_ratings": -2}]
+           {"rank1_max_ratings": -2}, {"kernel_variant": 4}, {"kernel_variant": -1}]
     for fields, want in [(f, 0) for f in good] + [(f, 1) for f in bad]:
         p, keep = _params(precision=2)
         shp = _lib.LaunchShape(**fields)
@@ -182,6 +182,43 @@ def test_autotune_candidates_follow_the_counts():
     assert not any(c.get("rank1_max_ratings") == 4 for c in mixed)   # no row has 4 ratings
     assert all(c.get("heavy_min_ratings", 0) <= 9000 for c in mixed)
     assert candidate_shapes([np.array([1, 9000])], 100) == [{}]     # K > 64: one launch shape
+    # a chosen kernel variant is kept in every candidate; without heavy splits none is listed
+    v = candidate_shapes([np.array([1, 2, 3, 9000, 50]), np.array([700, 20])], 64, heavy=False, variant=2)
+    assert v[0] == {"kernel_variant": 2} and all(c["kernel_variant"] == 2 for c in v)
+    assert not any(c.get("heavy_split") == 1 for c in v)
+
+
+def test_autotune_cost_model():
+    """The fixed-plus-per-rating fit recovers a, b from two launches, and the
+    heavy-split test asks whether the heaviest row outlasts its launch's share
+    (Section 4.2's workload model)."""
+    from paper_1705_10633_amd import autotune
+    a, b = autotune.fit_cost([(138493, 20_000_000, 0.004 * 138493 + 1.4e-5 * 2e7),
+                              (26744, 20_000_000, 0.004 * 26744 + 1.4e-5 * 2e7)])
+    assert abs(a - 0.004) < 1e-9 and abs(b - 1.4e-5) < 1e-12
+    flat = [np.full(100000, 150)]
+    assert not autotune.heavy_split_pays(flat, a, b)
+    assert autotune.heavy_split_pays([np.concatenate([np.full(1000, 3), [9000]])], a, b)
+    info = {"heavy_rows": (1, 0), "rank1_rows": (2, 0), "pieces": (4, 0)}
+    assert autotune.launch_rows([np.array([1, 1, 50, 9000]), np.array([3, 4])], info) == [(5, 9050), (2, 7)]
+
+
+def test_autotune_cache_keys(tmp_path):
+    """The cache answers only for the same GPU architecture, K, precision and
+    count histogram."""
+    from paper_1705_10633_amd import autotune
+    counts = [np.array([0, 1, 5, 900]), np.array([3, 903])]
+    key = autotune.problem_key(counts, 64, "bf16", "gfx950")
+    path = str(tmp_path / "cache.json")
+    assert autotune.cache_lookup(key, path) is None
+    autotune.cache_store(key, {"kernel_variant": 2}, [({}, 1.5)], [], path)
+    assert autotune.cache_lookup(key, path) == {"kernel_variant": 2}
+    assert autotune.cache_lookup(autotune.problem_key(counts, 64, "bf16", "gfx942"), path) is None
+    assert autotune.cache_lookup(autotune.problem_key(counts, 32, "bf16", "gfx950"), path) is None
+    other = [np.array([0, 1, 5, 9000]), np.array([3, 9003])]
+    assert autotune.cache_lookup(autotune.problem_key(other, 64, "bf16", "gfx950"), path) is None
+    autotune.cache_store(key, {"kernel_variant": 3}, [], [], path)
+    assert autotune.cache_lookup(key, path) == {"kernel_variant": 3}
 
 
 def test_autotune_result_round_trips(tmp_path):

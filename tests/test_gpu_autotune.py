@@ -61,19 +61,48 @@ def test_every_launch_shape_meets_the_oracle(precision, K):
         del s
 
 
+@pytest.mark.parametrize("precision,variant", [(p, v) for p in ("fp32", "bf16") for v in (1, 2, 3)])
+def test_every_kernel_variant_meets_the_oracle(precision, variant):
+    """The code variants of the one-wavefront K = 64 kernel (trailing updates
+    on matrix cores or vector units, 4 or 3 wavefronts per SIMD) sample the
+    same conditional: each meets the oracle at the arithmetic bound, with
+    heavy rows cut into pieces so the combine launch runs the variant too."""
+    K = 64
+    prob = _f32_start(_skewed(K, seed=K + 31))
+    tape = tape_for(prob, 1, seed=K + 33)
+    shape = {"kernel_variant": variant, "heavy_split": 1, "heavy_min_ratings": 1024, "piece_min_ratings": 256}
+    import torch
+    s = make_sampler(prob, precision=precision, with_test=False, shape=shape)
+    assert s.info()["kernel_variant"] == variant and s.info()["heavy_rows"][0] == 6
+    s.sweep(1, tape=_dev(tape))
+    torch.cuda.synchronize()
+    assert s.info()["fallback_rows"] == 0
+    check_arith(prob, s, tape, precision, f"variant {variant}")
+
+
 def test_autotune_returns_a_timed_candidate():
+    """K = 64: the three kernel variants are timed with the built-in cuts and
+    a cost model a rows + b ratings is fitted to each from its two row
+    launches; then the cut candidates of the fastest variant that the model
+    leaves in.  The kept shape is the fastest timed one."""
     from paper_1705_10633_amd import autotune
     from paper_1705_10633_amd.sampler import DeviceRatings
-    prob = _skewed(32, seed=5)
-    cands = autotune.candidate_shapes([prob.R.row_counts(), prob.R.col_counts()], prob.K)
-    assert len(cands) > 4
+    prob = _skewed(64, seed=5)
+    counts = [prob.R.row_counts(), prob.R.col_counts()]
     R = DeviceRatings(prob.R, val_dtype="float32")
     best, table = autotune.tune(R, prob.K, prob.U0.astype(np.float32), prob.V0.astype(np.float32),
-                                [prob.R.row_counts(), prob.R.col_counts()], precision="bf16",
-                                sweeps=3, warmup=1, mean_rating=prob.mean_rating)
-    assert [c for c, _ in table] == cands
-    assert all(ms > 0 for _, ms in table)
-    assert best in cands
+                                counts, precision="bf16", sweeps=3, warmup=1, mean_rating=prob.mean_rating)
+    fits = autotune.variant_fits()
+    assert [f["variant"] for f in fits] == [1, 2, 3]
+    assert [c for c, _ in table[:3]] == [{"kernel_variant": v} for v in (1, 2, 3)]
+    for f in fits:
+        print(f"variant {f['variant']}: {f['ms_per_sweep']:.3f} ms/sweep, a = {f['a_us_per_row']:.3g} us/row, "
+              f"b = {f['b_us_per_rating']:.3g} us/rating", flush=True)
+        assert f["ms_per_sweep"] > 0 and np.isfinite(f["a_us_per_row"]) and np.isfinite(f["b_us_per_rating"])
+        assert len(f["launches"]) == 2
+    fastest = min(fits, key=lambda f: f["ms_per_sweep"])["variant"]
+    assert all(c.get("kernel_variant") == fastest for c, _ in table[3:])
+    assert len(table) > 4 and all(ms > 0 for _, ms in table)
     assert min(ms for _, ms in table) == next(ms for c, ms in table if c == best)
 
 
@@ -123,12 +152,21 @@ def test_sampler_with_automatic_shape_meets_the_oracle():
     ref = O.gibbs(prob, tape, n_sweeps=1, nthreads=8)
     import torch
     from paper_1705_10633_amd.sampler import DeviceRatings, Sampler
-    s = Sampler(DeviceRatings(prob.R, val_dtype="float32"), K, prob.U0.astype(np.float32),
-                prob.V0.astype(np.float32), precision=precision, alpha=prob.alpha, beta0=prob.beta0,
-                nu0=prob.nu0, mean_rating=prob.mean_rating, shape="auto")
-    cands = autotune.candidate_shapes([prob.R.row_counts(), prob.R.col_counts()], K)
-    assert [c for c, _ in s.tune_table] == cands and s.shape in cands
+    import os
+    os.environ["BPMF_TUNE_CACHE"] = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"bpmf_tune_{os.getpid()}.json")
+    if os.path.exists(os.environ["BPMF_TUNE_CACHE"]):
+        os.remove(os.environ["BPMF_TUNE_CACHE"])
+    mk = lambda: Sampler(DeviceRatings(prob.R, val_dtype="float32"), K, prob.U0.astype(np.float32),
+                         prob.V0.astype(np.float32), precision=precision, alpha=prob.alpha, beta0=prob.beta0,
+                         nu0=prob.nu0, mean_rating=prob.mean_rating, shape="auto")
+    s = mk()
+    assert not s.tune_cached and s.shape in [c for c, _ in s.tune_table]
     print(f"kept {s.shape}", flush=True)
+    # the second sampler of the same problem takes the cached shape without tuning
+    again = mk()
+    assert again.tune_cached and again.shape == s.shape and again.tune_table is None
+    del again
+    os.remove(os.environ.pop("BPMF_TUNE_CACHE"))
     s.sweep(1, tape=_dev(tape))
     torch.cuda.synchronize()
     eu = row_rel_err(s.U.cpu().numpy(), ref["U"], MIXED_FLOOR)
