@@ -126,7 +126,7 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
     const bool mk = mixed && mixed_supported(K, p->precision);
     o.state = w.add(sizeof(DevState));
     for (int s = 0; s < 2; ++s) {
-        const int nc = stats_chunks(n[s]);
+        const int nc = stats_chunks(n[s], K);
         o.partials[s] = w.add(sizeof(double) * (size_t)nc * (K + K * (K + 1) / 2));
         o.sums[s] = w.add(sizeof(double) * (size_t)(K + K * (K + 1) / 2));
         o.scratch[s] = w.add(sizeof(double) * nw_scratch_doubles(K));
@@ -414,7 +414,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
     c->test_rows = d_test_rows;
     c->test_cols = d_test_cols;
     for (int sd = 0; sd < 2; ++sd) {
-        c->n_chunks[sd] = stats_chunks(n[sd]);
+        c->n_chunks[sd] = stats_chunks(n[sd], K);
         c->hyp[sd].Lambda = c->at<double>(off.lam[sd]);
         c->hyp[sd].mu = c->at<double>(off.mu[sd]);
         c->hyp[sd].Lmu = c->at<double>(off.lmu[sd]);

@@ -139,7 +139,7 @@ struct NwSide {
     HyperDev hyp;
 };
 hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s);
-int stats_chunks(int64_t n);
+int stats_chunks(int64_t n, int K);
 size_t nw_scratch_doubles(int K);
 hipError_t launch_stats_reduce(const StatsSides &ss, double *const sums[2], int K, hipStream_t s);
 hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double beta0, double nu0,

@@ -584,7 +584,15 @@ hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_
     return hipGetLastError();
 }
 
-int stats_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 511) / 512)); }
+// Row chunks of the side statistics: up to 256 of >= 512 rows for the
+// matrix-core kernel (K <= 64), whose per-chunk tree reduction and partial
+// write would otherwise dominate; up to 1024 of >= 128 rows above that, where
+// the per-row work is 4x larger and more blocks fill the device.
+int stats_chunks(int64_t n, int K)
+{
+    if (K <= 64) return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 511) / 512));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 127) / 128));
+}
 
 hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s)
 {
