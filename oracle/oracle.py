@@ -28,12 +28,26 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def build_sanitized(out: str) -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc, host code only) for the sanitizer test run; load it through the
+    BPMF_ORACLE_LIB environment variable with libasan preloaded."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wno-unused-variable",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-fno-omit-frame-pointer", "-o", out, SRC, "-lm", "-lpthread"])
+    return out
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build(force=True)
-        _lib = C.CDLL(LIB)
+        override = os.environ.get("BPMF_ORACLE_LIB")
+        if override:
+            _lib = C.CDLL(override)
+        else:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build(force=True)
+            _lib = C.CDLL(LIB)
         _declare(_lib)
     return _lib
 

@@ -17,6 +17,7 @@
 
 #include "../../include/bpmf.h"
 #include "common.hpp"
+#include "plan.hpp"
 
 namespace bpmf {
 size_t rows_f64_lds_bytes(int K);
@@ -208,48 +209,6 @@ struct bpmf_ctx {
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
-static bool host_cholesky(int n, const std::vector<double> &A, std::vector<double> &L)
-{
-    L.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j <= i; ++j) {
-            double s = A[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
-            if (i == j) {
-                if (!(s > 0.0) || !std::isfinite(s)) return false;
-                L[(size_t)i * n + i] = std::sqrt(s);
-            } else {
-                L[(size_t)i * n + j] = s / L[(size_t)j * n + j];
-            }
-        }
-    return true;
-}
-
-static bool host_spd_inverse(int n, const std::vector<double> &A, std::vector<double> &inv)
-{
-    std::vector<double> L;
-    if (!host_cholesky(n, A, L)) return false;
-    // inv = L^{-T} L^{-1}; first Li = L^{-1}
-    std::vector<double> Li((size_t)n * n, 0.0);
-    for (int c = 0; c < n; ++c) {
-        Li[(size_t)c * n + c] = 1.0 / L[(size_t)c * n + c];
-        for (int i = c + 1; i < n; ++i) {
-            double s = 0.0;
-            for (int m = c; m < i; ++m) s += L[(size_t)i * n + m] * Li[(size_t)m * n + c];
-            Li[(size_t)i * n + c] = -s / L[(size_t)i * n + i];
-        }
-    }
-    inv.assign((size_t)n * n, 0.0);
-    for (int a = 0; a < n; ++a)
-        for (int c = 0; c <= a; ++c) {
-            double s = 0.0;
-            for (int m = a; m < n; ++m) s += Li[(size_t)m * n + a] * Li[(size_t)m * n + c];
-            inv[(size_t)a * n + c] = s;
-            inv[(size_t)c * n + a] = s;
-        }
-    return true;
-}
-
 static bpmf_status check_params(const bpmf_ratings *R, const bpmf_params *p)
 {
     if (!R || !p) return fail(BPMF_E_INVALID, "NULL ratings or params");
@@ -288,20 +247,6 @@ static bpmf_status check_params(const bpmf_ratings *R, const bpmf_params *p)
     std::vector<double> W(p->W0, p->W0 + (size_t)p->K * p->K), L;
     if (!host_cholesky(p->K, W, L)) return fail(BPMF_E_NOT_SPD, "W0 is not positive definite");
     return BPMF_OK;
-}
-
-static bool check_structure(const std::vector<int64_t> &ptr, const std::vector<int32_t> &idx,
-                            int64_t n_other, std::string &why)
-{
-    if (ptr[0] != 0) { why = "pointer array must start at 0"; return false; }
-    for (size_t i = 0; i + 1 < ptr.size(); ++i) {
-        if (ptr[i + 1] < ptr[i]) { why = "pointer array decreases at " + std::to_string(i); return false; }
-        for (int64_t t = ptr[i]; t < ptr[i + 1]; ++t) {
-            if (idx[t] < 0 || idx[t] >= n_other) { why = "index out of range in row " + std::to_string(i); return false; }
-            if (t > ptr[i] && idx[t] <= idx[t - 1]) { why = "indices not strictly increasing in row " + std::to_string(i); return false; }
-        }
-    }
-    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -458,85 +403,25 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
     const LaunchShape shape = resolve_shape(p->shape, K);
     c->records = p->precision == BPMF_BF16 && mixed_supported(K, p->precision);
     c->variant = shape.variant;
-    // row order: rating count descending, ties by index
+    // row order (rating count descending, ties by index) and launch table
     for (int sd = 0; sd < 2; ++sd) {
-        std::vector<int32_t> ord(n[sd]);
-        std::iota(ord.begin(), ord.end(), 0);
-        const std::vector<int64_t> &pp = ptr[sd];
-        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
-            return pp[a + 1] - pp[a] > pp[b + 1] - pp[b];
-        });
-        HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.order[sd]), ord.data(), sizeof(int32_t) * n[sd], hipMemcpyHostToDevice, s));
-        auto entry = [&](int64_t q) {
-            const int64_t b = pp[ord[q]];
-            return make_int4(ord[q], (int)(pp[ord[q] + 1] - b), (int)(uint32_t)(uint64_t)b,
-                             (int)(uint32_t)((uint64_t)b >> 32));
-        };
-        int64_t nh = 0, ns = 0, nt = 0;
-        if (c->hyp[sd].Lchol) {
-            const int64_t lim = shape.rank1_max;
-            int64_t m = 0, t = 0;
-            while (m < n[sd] && pp[ord[n[sd] - 1 - m] + 1] - pp[ord[n[sd] - 1 - m]] <= lim) {
-                if (pp[ord[n[sd] - 1 - m] + 1] - pp[ord[n[sd] - 1 - m]] <= 1) ++t;
-                ++m;
-            }
-            // a short tail finishes inside the full kernel's launch anyway;
-            // a separate launch pays off once it is a sizeable share of the rows
-            const bool small_launch = shape.rank1_split > 0 ? m > 0
-                                      : (shape.rank1_split == 0 && (m >= 16384 || 16 * m >= n[sd]));
-            if (!small_launch) m = 0;
-            if (small_launch) {
-                ns = m;
-                nt = K <= 32 ? t : 0;
-            }
-            // heavy rows: worth the extra combine launch when they hold a
-            // sizeable share of the ratings (otherwise they finish inside
-            // the one-wavefront launch anyway)
-            int64_t hv = 0, hnnz = 0;
-            while (hv < n[sd] - m && hv < kMaxPieces / 2 && pp[ord[hv] + 1] - pp[ord[hv]] >= shape.heavy_min) {
-                hnnz += pp[ord[hv] + 1] - pp[ord[hv]];
-                ++hv;
-            }
-            if (shape.heavy_split > 0 || (shape.heavy_split == 0 && 10 * hnnz >= R->nnz)) nh = hv;
-            c->n_small[sd] = ns;
-            c->n_tiny[sd] = nt;
-        }
-        std::vector<int4> tab, ctab;
-        if (nh > 0) {
-            int64_t hnnz = 0;
-            for (int64_t q = 0; q < nh; ++q) hnnz += pp[ord[q] + 1] - pp[ord[q]];
-            // sum over rows of ceil(nnz / psz) <= hnnz / psz + nh <= kMaxPieces
-            const int64_t psz = std::max<int64_t>(shape.piece_min, (hnnz + kMaxPieces - nh - 1) / (kMaxPieces - nh));
-            for (int64_t q = 0; q < nh; ++q) {
-                const int64_t b = pp[ord[q]], e = pp[ord[q] + 1];
-                ctab.push_back(make_int4(ord[q], (int)tab.size(), 0, 0));
-                for (int64_t x = b; x < e; x += psz) {
-                    const int64_t cnt = std::min<int64_t>(psz, e - x);
-                    tab.push_back(make_int4(-(int)tab.size() - 1, (int)cnt, (int)(uint32_t)(uint64_t)x,
-                                            (int)(uint32_t)((uint64_t)x >> 32)));
-                }
-                ctab.back().z = (int)tab.size() - ctab.back().y;
-            }
-        }
-        c->n_heavy[sd] = nh;
-        c->n_pieces[sd] = (int64_t)tab.size();
-        for (int64_t q = nh; q < n[sd]; ++q) tab.push_back(entry(q));
-        c->n_entries[sd] = (int64_t)tab.size();
-        HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.rowtab[sd]), tab.data(), sizeof(int4) * tab.size(),
+        const PlanShape ps{shape.heavy_min, shape.piece_min, shape.rank1_max, shape.heavy_split, shape.rank1_split};
+        const SidePlan sp = plan_side(ptr[sd], n[sd], R->nnz, ps, c->hyp[sd].Lchol != nullptr, K, kMaxPieces,
+                                      c->records ? bf16_chunk(c->KP) : 0);
+        static_assert(sizeof(PlanEntry) == sizeof(int4), "launch-table entries are the kernels' int4");
+        HIP_OK_C(hipMemcpyAsync(c->at<int32_t>(off.order[sd]), sp.order.data(), sizeof(int32_t) * n[sd],
                                 hipMemcpyHostToDevice, s));
-        if (c->records) {
-            // first record of every entry (records are built once the FP32 ratings exist)
-            const int64_t chunk = bf16_chunk(c->KP);
-            std::vector<int64_t> roff(tab.size());
-            int64_t g = 0;
-            for (size_t e = 0; e < tab.size(); ++e) {
-                roff[e] = g;
-                g += (tab[e].y + chunk - 1) / chunk * (chunk / 4);
-            }
-            HIP_OK_C(hipMemcpyAsync(c->at<int64_t>(off.recoff[sd]), roff.data(), sizeof(int64_t) * roff.size(),
-                                    hipMemcpyHostToDevice, s));
-            HIP_OK_C(hipStreamSynchronize(s));
-        }
+        c->n_small[sd] = sp.n_small;
+        c->n_tiny[sd] = sp.n_tiny;
+        c->n_heavy[sd] = sp.n_heavy;
+        c->n_pieces[sd] = sp.n_pieces;
+        c->n_entries[sd] = (int64_t)sp.tab.size();
+        const std::vector<PlanEntry> &tab = sp.tab, &ctab = sp.ctab;
+        HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.rowtab[sd]), tab.data(), sizeof(PlanEntry) * tab.size(),
+                                hipMemcpyHostToDevice, s));
+        if (c->records)
+            HIP_OK_C(hipMemcpyAsync(c->at<int64_t>(off.recoff[sd]), sp.recoff.data(),
+                                    sizeof(int64_t) * sp.recoff.size(), hipMemcpyHostToDevice, s));
         if (!ctab.empty())
             HIP_OK_C(hipMemcpyAsync(c->at<int4>(off.ctab[sd]), ctab.data(), sizeof(int4) * ctab.size(),
                                     hipMemcpyHostToDevice, s));

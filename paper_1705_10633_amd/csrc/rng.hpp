@@ -71,14 +71,27 @@ __device__ __forceinline__ void box_muller_f64(u32x4 w, double &z0, double &z1)
 }
 
 // -log(u) for the 53-bit uniform u of (hi, lo), to a few FP32 ulps over all
-// of (0, 1).  Rounding u itself to FP32 would cost up to 2^-25 / (1 - u) of
-// relative accuracy near u = 1; there the exact complement 1 - u (the
-// uniform of the inverted 53 bits) is rounded instead and log1p is taken.
+// of (0, 1).  Rounding u itself to FP32 costs up to 2^-25 / (1 - u) of
+// relative accuracy near u = 1, so for v = 1 - u < 1/8 the series
+// -log(u) = sum_k v^k / k is used instead, with v the exact complement (the
+// uniform of the inverted 53 bits) rounded to FP32; nine terms leave a
+// truncation error below v^9 / 10 < 2^-27 relative.  Both forms are
+// evaluated and one is selected, so no lane waits for a branch.
 __device__ __forceinline__ float neglog_uniform53_f32(uint32_t hi, uint32_t lo)
 {
     const float u = uniform53_f32(hi, lo);
     const float v = uniform53_f32(~hi, ~lo);
-    return u < 0.5f ? -logf(u) : -log1pf(-v);
+    float s = 1.0f / 9.0f;
+    s = fmaf(s, v, 1.0f / 8.0f);
+    s = fmaf(s, v, 1.0f / 7.0f);
+    s = fmaf(s, v, 1.0f / 6.0f);
+    s = fmaf(s, v, 1.0f / 5.0f);
+    s = fmaf(s, v, 1.0f / 4.0f);
+    s = fmaf(s, v, 1.0f / 3.0f);
+    s = fmaf(s, v, 0.5f);
+    s = fmaf(s, v, 1.0f);
+    const float lg = -logf(u);
+    return v < 0.125f ? v * s : lg;
 }
 
 __device__ __forceinline__ void box_muller_f32(u32x4 w, float &z0, float &z1)
