@@ -201,6 +201,8 @@ def main():
                     help="time every candidate launch shape first and sweep with the fastest")
     ap.add_argument("--shape", default=None,
                     help="launch shape to sweep with, as JSON (bpmf_launch_shape fields)")
+    ap.add_argument("--users-by-count", action="store_true",
+                    help="renumber the users in descending rating count first (reordering of R for locality)")
     ap.add_argument("--only-timed", action="store_true",
                     help="run only warm-up and timed sweeps (for profiler runs)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -231,6 +233,8 @@ def main():
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     prob = getattr(synth, wl["gen"])()
+    if args.users_by_count:
+        prob = synth.relabel_users_by_count(prob)
     K = prob.K
     prec = wl["precision"]
     log(f"[bench] workload generated in {time.perf_counter() - t0:.1f} s: M={prob.M} N={prob.N} "

@@ -458,6 +458,29 @@ def foldin_requests(n: int, N: int, seed=105, mu=3.0, sigma=1.5, cap=5000, Q=100
     return FoldinRequests(n, ptr, cols, vals, q_ptr, q_cols, arrival)
 
 
+def relabel_users_by_count(prob: Problem) -> Problem:
+    """The same problem with the users renumbered in descending rating count
+    (ties by the old index): the reordering of R's rows for locality that
+    the paper applies before its runs (Section 3.1), here so that the users
+    gathered most often on the movies' side share pages and cache sets.  U0
+    and the held-out pairs are permuted with them; the posterior is the same
+    up to the relabelling."""
+    R = prob.R
+    counts = R.row_counts()
+    new_of_old = np.empty(R.M, np.int64)
+    new_of_old[np.argsort(-counts, kind="stable")] = np.arange(R.M)
+    rows = new_of_old[np.repeat(np.arange(R.M), counts)]
+    R2 = from_coo(R.M, R.N, rows, R.col_idx.astype(np.int64), R.row_val)
+    p = Problem(**{**prob.__dict__})
+    p.R = R2
+    U0 = np.empty_like(prob.U0)
+    U0[new_of_old] = prob.U0
+    p.U0 = U0
+    p.test_rows = new_of_old[prob.test_rows].astype(np.int32)
+    p.name = prob.name + "_users_by_count"
+    return p
+
+
 CONFIGS = {
     "uniform_planted": uniform_planted,
     "chembl_like": chembl_like,

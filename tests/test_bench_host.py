@@ -42,3 +42,27 @@ def test_cpu_baseline_whole_sweeps_and_row_sample():
     assert part["cores"] == 1 and part["value"] > 0 and "sample of the rows" in part["sample"]
     assert isinstance(bench.host_cpu_model(), str)
 
+
+
+def test_users_by_count_relabelling_is_a_permutation():
+    """The reordering option renumbers users in descending rating count and
+    carries U0 and the held-out pairs along: the same ratings, the same
+    predictions from the same factors."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1705_10633_amd import synth
+    p = synth.uniform_planted(M=300, N=120, K=4, nnz=4000, seed=9, n_sweeps=1)
+    q = synth.relabel_users_by_count(p)
+    c = q.R.row_counts()
+    assert np.all(c[:-1] >= c[1:]) and q.R.nnz == p.R.nnz
+    assert sorted(c.tolist()) == sorted(p.R.row_counts().tolist())
+    np.testing.assert_array_equal(O.predict(p.U0, p.V0, p.test_rows, p.test_cols, 3.0),
+                                  O.predict(q.U0, q.V0, q.test_rows, q.test_cols, 3.0))
+    # each user's set of (movie, rating) pairs is kept
+    new_of_old = np.empty(300, np.int64)
+    new_of_old[np.argsort(-p.R.row_counts(), kind="stable")] = np.arange(300)
+    for u in (0, 17, 299):
+        a = p.R.col_idx[p.R.row_ptr[u]:p.R.row_ptr[u + 1]]
+        v = new_of_old[u]
+        b = q.R.col_idx[q.R.row_ptr[v]:q.R.row_ptr[v + 1]]
+        np.testing.assert_array_equal(a, b)
