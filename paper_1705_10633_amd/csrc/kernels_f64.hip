@@ -399,6 +399,95 @@ __global__ __launch_bounds__(STATS_THREADS) void stats_mfma_kernel(StatsSides ss
             }
 }
 
+// Side statistics on FP64 matrix cores for 64 < K <= 128: the 36 lower
+// 16 x 16 tiles of sum x x^T are dealt to the eight wavefronts of a block
+// (tile t to wavefront t % 8, at most five each), so every wavefront runs
+// every row of the chunk through its own tiles and no reduction across
+// wavefronts is needed.  Rows are staged 32 at a time in LDS (FP32 as
+// stored), one coalesced load per thread and row block; wavefront 0 also
+// sums x.  Padding features (K <= f < 128) are zero.
+constexpr int SB_NB = 8;
+constexpr int SB_NT = SB_NB * (SB_NB + 1) / 2;
+constexpr int SB_ROWS = 32;
+
+__device__ __forceinline__ void tile_ab(int t, int &a, int &b)
+{
+    a = 0;
+    while ((a + 1) * (a + 2) / 2 <= t) ++a;
+    b = t - a * (a + 1) / 2;
+}
+
+template <typename XT>
+__global__ __launch_bounds__(STATS_THREADS) void stats_mfma_big_kernel(StatsSides ss, int K)
+{
+    __shared__ double stage[SB_ROWS][SB_NB * 16 + 1];
+    const int side = (int)blockIdx.x >= ss.n_chunks[0] ? 1 : 0;
+    const XT *X = (const XT *)ss.X[side];
+    const int64_t n = ss.n[side];
+    double *partials = ss.partials[side];
+    const int n_chunks = ss.n_chunks[side];
+    const int chunk = (int)blockIdx.x - (side ? ss.n_chunks[0] : 0);
+    constexpr int NWV = STATS_THREADS / 64;
+    constexpr int TPW = (SB_NT + NWV - 1) / NWV;  // tiles per wavefront (5)
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i16 = lane & 15, g = lane >> 4;
+    const int64_t r0 = n * chunk / n_chunks, r1 = n * (chunk + 1) / n_chunks;
+    f64x4 acc[TPW];
+    int ta[TPW], tb[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        const int t = wave + NWV * j;
+        tile_ab(t < SB_NT ? t : 0, ta[j], tb[j]);
+    }
+    double sx[SB_NB];
+#pragma unroll
+    for (int b = 0; b < SB_NB; ++b) sx[b] = 0.0;
+    for (int64_t c0 = r0; c0 < r1; c0 += SB_ROWS) {
+        const int cnt = (int)min((int64_t)SB_ROWS, r1 - c0);
+        for (int e = tid; e < SB_ROWS * SB_NB * 16; e += STATS_THREADS) {
+            const int q = e / (SB_NB * 16), f = e - q * (SB_NB * 16);
+            // clamped indices, zero beyond the chunk and the padding features
+            stage[q][f] = (double)X[(c0 + (q < cnt ? q : cnt - 1)) * K + (f < K ? f : K - 1)] *
+                          ((q < cnt && f < K) ? 1.0 : 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SB_ROWS / 4; ++u) {
+            const double *xr = stage[4 * u + g];
+#pragma unroll
+            for (int j = 0; j < TPW; ++j)
+                if (wave + NWV * j < SB_NT)
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[16 * ta[j] + i16], xr[16 * tb[j] + i16], acc[j],
+                                                                  0, 0, 0);
+            if (wave == 0)
+#pragma unroll
+                for (int b = 0; b < SB_NB; ++b) sx[b] += xr[16 * b + i16];
+        }
+        __syncthreads();
+    }
+    double *out = partials + (int64_t)chunk * (K + K * (K + 1) / 2);
+    if (wave == 0) {
+#pragma unroll
+        for (int b = 0; b < SB_NB; ++b) {
+            double v = sx[b];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            const int f = 16 * b + i16;
+            if (g == 0 && f < K) out[f] = v;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        if (wave + NWV * j >= SB_NT) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = 16 * ta[j] + 4 * v + g, cc = 16 * tb[j] + i16;
+            if (rr < K && cc <= rr) out[K + rr * (rr + 1) / 2 + cc] = acc[j][v];
+        }
+    }
+}
+
 // 16 lanes per group of 4 consecutive (row-sorted) pairs: all eight factor
 // row reads of a lane are issued together, FP64 accumulation, shuffle
 // reduction inside the 16-lane group.
@@ -614,6 +703,15 @@ hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s
             else BPMF_STATS_MFMA(float, 4);
         }
 #undef BPMF_STATS_MFMA
+        return hipGetLastError();
+    }
+    if (K <= SB_NB * 16) {
+        const unsigned grid = (unsigned)(ss.n_chunks[0] + ss.n_chunks[1]);
+        if (grid == 0) return hipSuccess;
+        if (x_is_f64)
+            hipLaunchKernelGGL((stats_mfma_big_kernel<double>), dim3(grid), dim3(STATS_THREADS), 0, s, ss, K);
+        else
+            hipLaunchKernelGGL((stats_mfma_big_kernel<float>), dim3(grid), dim3(STATS_THREADS), 0, s, ss, K);
         return hipGetLastError();
     }
     const int nb = (K + 3) >> 2;

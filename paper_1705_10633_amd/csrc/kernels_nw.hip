@@ -302,14 +302,13 @@ __global__ __launch_bounds__(NWP_THREADS) void nw_packed_kernel(NwSide side0, Nw
         }
         for (int i = tid; i < k; i += NWP_THREADS) PL[ptri(k, i)] *= inv;
         __syncthreads();
-        // leading block: PL(ii, jj) -= R_ii,k R_jj,k for jj <= ii < k
+        // leading block: PL(ii, jj) -= R_ii,k R_jj,k for jj <= ii < k; 32
+        // rows at a time, 16 threads along a row
         const double *rk = PL + ptri(k, 0);
-        for (int e = tid; e < ptri(k, 0); e += NWP_THREADS) {
-            int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-            while (ptri(ii, 0) > e) --ii;
-            while (ptri(ii + 1, 0) <= e) ++ii;
-            const int jj = e - ptri(ii, 0);
-            PL[e] = fma(-rk[ii], rk[jj], PL[e]);
+        for (int ii = tid >> 4; ii < k; ii += NWP_THREADS / 16) {
+            const double r = rk[ii];
+            double *row = PL + ptri(ii, 0);
+            for (int jj = tid & 15; jj <= ii; jj += 16) row[jj] = fma(-r, rk[jj], row[jj]);
         }
     }
     __syncthreads();
@@ -317,11 +316,11 @@ __global__ __launch_bounds__(NWP_THREADS) void nw_packed_kernel(NwSide side0, Nw
     // the rows below (TL(i, c) -= R_mi T_mc for i > m, c <= m)
     for (int m = 0; m < K; ++m) {
         const double irm = 1.0 / rd[m];
-        const int rows = K - 1 - m, cols = m + 1;
-        for (int e = tid; e < rows * cols; e += NWP_THREADS) {
-            const int ii = e / cols, c = e - ii * cols;
-            const int i = m + 1 + ii;
-            TL[ptri(i, c)] = fma(-PL[ptri(i, m)], TL[ptri(m, c)] * irm, TL[ptri(i, c)]);
+        const double *tm = TL + ptri(m, 0);
+        for (int i = m + 1 + (tid >> 4); i < K; i += NWP_THREADS / 16) {
+            const double rmi = PL[ptri(i, m)] * irm;
+            double *ti = TL + ptri(i, 0);
+            for (int c = tid & 15; c <= m; c += 16) ti[c] = fma(-rmi, tm[c], ti[c]);
         }
         __syncthreads();
         for (int c = tid; c <= m; c += NWP_THREADS) TL[ptri(m, c)] *= irm;
