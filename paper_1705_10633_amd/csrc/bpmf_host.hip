@@ -68,7 +68,7 @@ struct WsLayout {
 };
 
 struct Offsets {
-    size_t state, partials[2], sums[2], scratch[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], lamacc[2], lchol[2], nwd[2], mu0, w0inv,
+    size_t state, partials[2], sums[2], lam[2], mu[2], lmu[2], lamf[2], lmuf[2], lamt[2], lamacc[2], lchol[2], nwd[2], mu0, w0inv,
         order[2], rowtab[2], recoff[2], rec[2], ctab[2], part[2], fblist[2], shadow[2], valsf[2], accum, trows, tcols, tperm, reduce;
     size_t total;
 };
@@ -130,7 +130,6 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
         const int nc = stats_chunks(n[s], K);
         o.partials[s] = w.add(sizeof(double) * (size_t)nc * (K + K * (K + 1) / 2));
         o.sums[s] = w.add(sizeof(double) * (size_t)(K + K * (K + 1) / 2));
-        o.scratch[s] = w.add(sizeof(double) * nw_scratch_doubles(K));
         o.lam[s] = w.add(sizeof(double) * K * K);
         o.mu[s] = w.add(sizeof(double) * K);
         o.lmu[s] = w.add(sizeof(double) * K);
@@ -235,6 +234,9 @@ static bpmf_status check_params(const bpmf_ratings *R, const bpmf_params *p)
     }
     if (R->M < 1 || R->N < 1 || R->nnz < 0) return fail(BPMF_E_INVALID, "M, N must be >= 1, nnz >= 0");
     if (R->M > INT32_MAX || R->N > INT32_MAX) return fail(BPMF_E_INVALID, "M and N must fit in int32");
+    // the K <= 64 BF16 gathers address rows with 32-bit byte offsets
+    if (p->precision == BPMF_BF16 && p->K <= 64 && (R->M >= (1 << 24) || R->N >= (1 << 24)))
+        return fail(BPMF_E_INVALID, "BF16 precision with K <= 64 needs M and N below 2^24");
     if (!R->d_row_ptr || !R->d_col_ptr) return fail(BPMF_E_INVALID, "NULL row_ptr/col_ptr");
     if (R->nnz > 0 && (!R->d_col_idx || !R->d_row_val || !R->d_row_idx || !R->d_col_val))
         return fail(BPMF_E_INVALID, "NULL index or value array");
@@ -563,7 +565,6 @@ static bpmf_status enqueue_hyper(bpmf_ctx *c, const DrawSrc &d0, const DrawSrc &
         nw[sd].n = ss.n[sd];
         nw[sd].draws = *d[sd];
         if (pre) nw[sd].draws.tape_nw = ss.draw_out[sd];
-        nw[sd].scratch = c->at<double>(c->off.scratch[sd]);
         nw[sd].hyp = c->hyp[sd];
     }
     t0 = time_begin(c, s);

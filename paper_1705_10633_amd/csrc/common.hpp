@@ -135,12 +135,10 @@ struct NwSide {
     const double *sums;    // sum x (K) then sum x x^T (packed lower, K(K+1)/2)
     int64_t n;
     DrawSrc draws;
-    double *scratch;       // K > 64 only
     HyperDev hyp;
 };
 hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s);
 int stats_chunks(int64_t n, int K);
-size_t nw_scratch_doubles(int K);
 hipError_t launch_stats_reduce(const StatsSides &ss, double *const sums[2], int K, hipStream_t s);
 hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double beta0, double nu0,
                      const double *W0inv, DevState *state, hipStream_t s);

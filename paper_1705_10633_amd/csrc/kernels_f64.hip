@@ -198,72 +198,6 @@ __global__ __launch_bounds__(256) void rows_f64_kernel(SideArgs a, int K, double
     }
 }
 
-// Side statistics: per chunk of rows, sum_i x_i (K) and the lower triangle of
-// sum_i x_i x_i^T (K(K+1)/2, packed by rows), in FP64.
-template <typename XT, int MT>
-__global__ __launch_bounds__(256) void stats_kernel(const XT *X, int64_t n, int K, double *partials,
-                                                    int n_chunks)
-{
-    __shared__ double stage[32 * 132];
-    const int tid = threadIdx.x;
-    const int nb = (K + 3) >> 2;
-    const int KS = nb * 4;
-    const int T = nb * (nb + 1) / 2;
-    const int E = K + K * (K + 1) / 2;
-    const int64_t r0 = n * blockIdx.x / n_chunks, r1 = n * (blockIdx.x + 1) / n_chunks;
-    int tr[MT], tc[MT];
-    bool tv[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        int t = tid + 256 * m;
-        tv[m] = t < T;
-        tri_decode(tv[m] ? t : 0, tr[m], tc[m]);
-    }
-    double acc[MT][16];
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[m][e] = 0.0;
-    double sacc = 0.0;
-    for (int64_t c0 = r0; c0 < r1; c0 += 32) {
-        const int cnt = (int)min((int64_t)32, r1 - c0);
-        for (int e = tid; e < 32 * KS; e += 256) {
-            int q = e / KS, f = e - q * KS;
-            stage[e] = (double)X[(c0 + (q < cnt ? q : cnt - 1)) * K + (f < K ? f : K - 1)] * ((q < cnt && f < K) ? 1.0 : 0.0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            if (!tv[m]) continue;
-            for (int q = 0; q < cnt; ++q) {
-                const double *sr = stage + q * KS;
-                double xs[4] = {sr[4 * tr[m]], sr[4 * tr[m] + 1], sr[4 * tr[m] + 2], sr[4 * tr[m] + 3]};
-                double ys[4] = {sr[4 * tc[m]], sr[4 * tc[m] + 1], sr[4 * tc[m] + 2], sr[4 * tc[m] + 3]};
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[m][i * 4 + j] = fma(xs[i], ys[j], acc[m][i * 4 + j]);
-            }
-        }
-        if (tid < K)
-            for (int q = 0; q < cnt; ++q) sacc += stage[q * KS + tid];
-        __syncthreads();
-    }
-    double *out = partials + (int64_t)blockIdx.x * E;
-    if (tid < K) out[tid] = sacc;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        if (!tv[m]) continue;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                int r = 4 * tr[m] + i, c = 4 * tc[m] + j;
-                if (r < K && c <= r) out[K + r * (r + 1) / 2 + c] = acc[m][i * 4 + j];
-            }
-    }
-}
-
 // Side statistics on FP64 matrix cores (K <= 64): one wavefront per chunk of
 // rows; every 4 rows feed v_mfma_f64_16x16x4_f64 for each lower 16x16 tile
 // of sum x x^T (operand lane l = row l/16 of the group, feature l%16 of the
@@ -714,24 +648,7 @@ hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s
             hipLaunchKernelGGL((stats_mfma_big_kernel<float>), dim3(grid), dim3(STATS_THREADS), 0, s, ss, K);
         return hipGetLastError();
     }
-    const int nb = (K + 3) >> 2;
-    const bool big = nb * (nb + 1) / 2 > 256;
-    for (int sd = 0; sd < 2; ++sd) {
-        const int64_t n = ss.n[sd];
-        const int nc = ss.n_chunks[sd];
-        if (nc == 0) continue;
-        double *partials = ss.partials[sd];
-        if (x_is_f64) {
-            if (big) hipLaunchKernelGGL((stats_kernel<double, 3>), dim3(nc), dim3(256), 0, s, (const double *)ss.X[sd], n, K, partials, nc);
-            else hipLaunchKernelGGL((stats_kernel<double, 1>), dim3(nc), dim3(256), 0, s, (const double *)ss.X[sd], n, K, partials, nc);
-        } else {
-            if (big) hipLaunchKernelGGL((stats_kernel<float, 3>), dim3(nc), dim3(256), 0, s, (const float *)ss.X[sd], n, K, partials, nc);
-            else hipLaunchKernelGGL((stats_kernel<float, 1>), dim3(nc), dim3(256), 0, s, (const float *)ss.X[sd], n, K, partials, nc);
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return hipErrorInvalidValue;
 }
 
 // FP32 factors with K a multiple of 4 and at most 64: lane l of a 16-lane
