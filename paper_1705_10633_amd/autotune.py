@@ -160,8 +160,11 @@ def time_variant(ratings: DeviceRatings, K: int, U0, V0, row_counts, variant: in
 
 def heavy_split_pays(row_counts: Sequence[np.ndarray], a: float, b: float, slots: int = WAVE_SLOTS) -> bool:
     """Whether some side's heaviest row outlasts its launch's share of the
-    work under the cost model (a per row, b per rating, `slots` rows at once)."""
-    if not (np.isfinite(a) and np.isfinite(b)):
+    work under the cost model (a per row, b per rating, `slots` rows at once).
+    A fit that is not a cost (not finite, a < 0 or b <= 0: the two launches
+    did not follow the model, e.g. when rows of very different kinds share a
+    launch) rules nothing out."""
+    if not (np.isfinite(a) and np.isfinite(b)) or a < 0 or b <= 0:
         return True
     for c in row_counts:
         c = np.asarray(c, np.float64)

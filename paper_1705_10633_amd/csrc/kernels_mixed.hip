@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
     using S = RowShape<KP>;
     constexpr int PW = piece_floats(KP);
     __shared__ __attribute__((aligned(16))) float u[S::UNION];
-    __shared__ __attribute__((aligned(16))) float rv[64];
+    __shared__ __attribute__((aligned(16))) float rv[96];
     __shared__ __attribute__((aligned(16))) float colbuf[3 * KP];
     __shared__ int sidx[16];
 

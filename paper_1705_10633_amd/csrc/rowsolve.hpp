@@ -16,6 +16,7 @@ namespace bpmf {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <int KP>
 struct RowShape {
@@ -59,16 +60,30 @@ struct WaveSync {
 // feature-major so each lane's matrix-core operand (8 consecutive ratings of
 // one feature) is one 16-byte LDS read.
 //
-// The right-hand side sum_j r'_j v_j runs on v_dot2c_f32_bf16 over pairs of
-// ratings with r' = hi + lo carried to about 2^-17 relative; `rvp` holds the
-// chunk's CH / 2 packed hi pairs followed by its CH / 2 lo pairs.
+// The right-hand side sum_j r'_j v_j, with r' = hi + lo carried to about
+// 2^-17 relative, runs on the matrix cores too: v_mfma_f32_16x16x32_bf16 with
+// A = the 16 x 32 matrix whose row 0 holds the hi parts of 32 ratings, row 1
+// their lo parts and the other rows zeros, and B = the 32 ratings' staged
+// features 16t..16t+15, so C[0][f] and C[1][f] collect the hi and lo sums of
+// feature 16t + f.  `rvp` holds the chunk's CH / 2 packed hi pairs, its CH / 2
+// lo pairs and CH / 2 zero words (3 CH / 2 words).
 template <int KP, class Sync = BlockSync>
 __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const uint16_t *src, int stride,
                                           char *stage, uint32_t *rvp, floatx16 *acc, float &bacc)
 {
     using S = RowShape<KP>;
     static_assert(S::CH == bf16_chunk(KP), "records are padded to the kernel's chunk");
+    static_assert(S::CH % 32 == 0, "the right-hand side takes 32 ratings per step");
+    constexpr int NG = KP / 16;   // 16-feature groups of the right-hand side
     const int lane = threadIdx.x & 63;
+    floatx4 bq[NG];
+#pragma unroll
+    for (int t = 0; t < NG; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bq[t][e] = 0.0f;
+    // rows 2..15 of the right-hand side's A operand read the zero words
+    if (lane < S::CH / 2) rvp[S::CH + lane] = 0u;
+    const uint4 *aop = (const uint4 *)(rvp + (lane % 16 < 2 ? lane % 16 : 2) * (S::CH / 2)) + lane / 16;
     // lanes 0..RG-1 stage feature block 0, lanes RG..2RG-1 block 1, ...: the
     // 8-byte staging writes of a quarter-wave then spread over more banks
     // than with consecutive lanes on consecutive feature blocks
@@ -76,11 +91,15 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
     const int64_t nch = (nnz + S::CH - 1) / S::CH;
     // Loaded values stay raw until they are used (a chunk later), so no
     // arithmetic right after a load forces a wait for the loads in flight.
+    // 32-bit byte offsets from the uniform base (the host keeps each side
+    // below 2^24 rows, so they fit): one multiply-add per load
+    const char *base = (const char *)src;
+    const uint32_t rowb = 2u * (uint32_t)stride, fbb = 16u * (uint32_t)fb;
     auto load_rows = [&](const uint4 &c, uint4 *d) {
-        d[0] = *(const uint4 *)(src + (int64_t)(int)c.x * stride + fb * 8);
-        d[1] = *(const uint4 *)(src + (int64_t)(int)c.y * stride + fb * 8);
-        d[2] = *(const uint4 *)(src + (int64_t)(int)c.z * stride + fb * 8);
-        d[3] = *(const uint4 *)(src + (int64_t)(int)c.w * stride + fb * 8);
+        d[0] = *(const uint4 *)(base + (__umul24(c.x, rowb) + fbb));
+        d[1] = *(const uint4 *)(base + (__umul24(c.y, rowb) + fbb));
+        d[2] = *(const uint4 *)(base + (__umul24(c.z, rowb) + fbb));
+        d[3] = *(const uint4 *)(base + (__umul24(c.w, rowb) + fbb));
     };
     // r' pairs and the feature-major copy of one chunk into LDS
     auto stage_chunk = [&](const uint4 *d, const uint4 &rp) {
@@ -95,11 +114,12 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const int f = fb * 8 + 2 * w;
+            // v_perm_b32 byte selects: low halves of (w0, w1), high halves
             uint2 lo, hi;
-            lo.x = (w0[w] & 0xffffu) | (w1[w] << 16);
-            lo.y = (w2[w] & 0xffffu) | (w3[w] << 16);
-            hi.x = (w0[w] >> 16) | (w1[w] & 0xffff0000u);
-            hi.y = (w2[w] >> 16) | (w3[w] & 0xffff0000u);
+            lo.x = __builtin_amdgcn_perm(w1[w], w0[w], 0x05040100u);
+            lo.y = __builtin_amdgcn_perm(w3[w], w2[w], 0x05040100u);
+            hi.x = __builtin_amdgcn_perm(w1[w], w0[w], 0x07060302u);
+            hi.y = __builtin_amdgcn_perm(w3[w], w2[w], 0x07060302u);
             *(uint2 *)(stage + f * S::SB + rg * 8) = lo;
             *(uint2 *)(stage + (f + 1) * S::SB + rg * 8) = hi;
         }
@@ -117,27 +137,16 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
                 acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, acc[2], 0, 0, 0);
             }
         }
-        constexpr int SPLIT = 64 / KP;
-        constexpr int PAIRS = S::CH / SPLIT / 2;
-        static_assert(PAIRS % 4 == 0, "rhs pairs are read four at a time");
-        const int f = lane % KP, part = lane / KP;
-        const uint4 *sp = (const uint4 *)(stage + f * S::SB) + part * (PAIRS / 4);
-        const uint4 *hp = (const uint4 *)rvp + part * (PAIRS / 4);
-        const uint4 *lp = (const uint4 *)(rvp + S::CH / 2) + part * (PAIRS / 4);
 #pragma unroll
-        for (int p4 = 0; p4 < PAIRS / 4; ++p4) {
-            const uint4 sv = sp[p4], hv = hp[p4], lv = lp[p4];
-            const uint32_t sa[4] = {sv.x, sv.y, sv.z, sv.w};
-            const uint32_t ha[4] = {hv.x, hv.y, hv.z, hv.w};
-            const uint32_t la[4] = {lv.x, lv.y, lv.z, lv.w};
+        for (int ks = 0; ks < S::CH / 32; ++ks) {
+            // A: lane l holds row l % 16, ratings 32 ks + 8 (l / 16) .. + 7
+            const bf16x8_t Ar = *(const bf16x8_t *)(aop + 4 * ks);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                bf16x2_t x, yh, yl;
-                __builtin_memcpy(&x, &sa[q], 4);
-                __builtin_memcpy(&yh, &ha[q], 4);
-                __builtin_memcpy(&yl, &la[q], 4);
-                bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yh, bacc, false);
-                bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yl, bacc, false);
+            for (int t = 0; t < NG; ++t) {
+                // B: lane l holds feature 16 t + l % 16 of the same ratings
+                const bf16x8_t Bf =
+                    *(const bf16x8_t *)(stage + (16 * t + lane % 16) * S::SB + (ks * 32 + (lane / 16) * 8) * 2);
+                bq[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Bf, bq[t], 0, 0, 0);
             }
         }
     };
@@ -170,7 +179,15 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
         multiply_chunk();
         Sync::sync();
     }
-    if constexpr (KP == 32) bacc += __shfl_xor(bacc, 32);
+    // lane c < 16 of bq[t] holds the hi (element 0) and lo (element 1) sums of
+    // feature 16 t + c; lane l takes feature l % KP
+    float bsum = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NG; ++t) {
+        const float v = __shfl(bq[t][0] + bq[t][1], lane % 16);
+        bsum = (lane % KP) / 16 == t ? v : bsum;
+    }
+    bacc += bsum;
 }
 
 // FP32 gathers of rows `idx` of `src` (row stride K), Gram on FP32 matrix cores.
@@ -351,6 +368,54 @@ __device__ __forceinline__ void gemm_cols16_31(float *A)
         }
 }
 
+// Columns C0..C0+7 from the factored panel K0..K0+7 (K0 + 8 = C0), on the
+// matrix cores: A[r][c] -= sum_{k in K0..K0+7} L[r][k] L[c][k].  C0 < 32: for
+// all 64 rows as in gemm_cols16_31 (D0 for rows 0..31, D1 for rows 32..63);
+// C0 >= 32: for rows 32..63 as in syrk_lower_rows (rows 0..31 have no entries
+// there left of their diagonal).
+template <int K0, int C0>
+__device__ __forceinline__ void next8_mfma(float *A)
+{
+    static_assert(K0 + 8 == C0 && C0 % 8 == 0 && C0 < 64, "next panel of a factored panel");
+    if constexpr (C0 < 32) {
+        floatx16 d0 = {}, d1 = {};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[K0 + 2 * kk]),
+                                                             __float_as_uint(A[K0 + 2 * kk + 1]), false, false);
+            const float xa = __uint_as_float(sw[0]), xb = __uint_as_float(sw[1]);
+            d0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xa, d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xb, d1, 0, 0, 0);
+        }
+        constexpr int j = C0 / 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(d0[4 * j + i]),
+                                                             __float_as_uint(d1[4 * j + i]), false, false);
+            A[8 * j + i] -= __uint_as_float(sw[0]);
+            A[8 * j + 4 + i] -= __uint_as_float(sw[1]);
+        }
+    } else {
+        floatx16 c = {};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[K0 + 2 * kk]),
+                                                             __float_as_uint(A[K0 + 2 * kk + 1]), false, false);
+            const float x = __uint_as_float(sw[1]);
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(x, x, c, 0, 0, 0);
+        }
+        constexpr int j = (C0 - 32) / 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float own = c[4 * j + i];
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(own), __float_as_uint(own),
+                                                             false, false);
+            A[32 + 8 * j + 4 + i] -= own;
+            A[32 + 8 * j + i] -= __uint_as_float(sw[0]);
+        }
+    }
+}
+
 // Columns c0..c0+7 of the matrix whose row ri = lane % KP is in A: column k
 // is scaled by 1/sqrt(P_kk) (lane k thereby holds L_kk, invbuf[k] = 1/L_kk)
 // and the later panel columns are updated with values read across lanes with
@@ -416,7 +481,7 @@ __device__ __forceinline__ void chol_panel(float (&A)[KP], float *invbuf, float 
 template <int P, class Sync>
 __device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf, float *pbuf)
 {
-    if constexpr (P == 1 || P == 3 || P == 5 || P == 7) chol_next<64, Sync>(A, pbuf, 8 * (P - 1), 8 * (P + 1));
+    if constexpr (P == 1 || P == 3 || P == 5 || P == 7) next8_mfma<8 * (P - 1), 8 * P>(A);
     if constexpr (P == 2) gemm_cols16_31(A);
     if constexpr (P == 4) syrk_lower_rows<0, 32, 0>(A);
     if constexpr (P == 6) syrk_lower_rows<32, 16, 2>(A);
@@ -432,14 +497,14 @@ __device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf, float
 // masks.  An unusable pivot gives a NaN, infinite or zero 1/sqrt, caught by
 // chol_pivots_fail.
 //
-// KP = 64: the panels' updates reach only the next panel of their 16-column
-// block on the vector units; everything further right is a matrix-core
-// product: columns 16..31 of all rows from columns 0..15 (gemm_cols16_31),
-// the trailing 32 x 32 block A22 -= L21 L21^T from columns 0..31, and
-// columns 48..63 of rows 32..63 from columns 32..47 (syrk_lower_rows).
-// That leaves 480 multiply-add instructions per lane on the vector units (224
-// inside the panels, 256 for the next panel), against 992 when only A22 was
-// a matrix-core product.
+// KP = 64: every update beyond a panel's own 8 columns is a matrix-core
+// product: the next panel from the one just factored (next8_mfma), columns
+// 16..31 of all rows from columns 0..15 (gemm_cols16_31), the trailing
+// 32 x 32 block A22 -= L21 L21^T from columns 0..31, and columns 48..63 of
+// rows 32..63 from columns 32..47 (syrk_lower_rows).  That leaves the 224
+// multiply-add instructions per lane inside the panels on the vector units,
+// against 480 with the next-panel updates there and 992 when only A22 was a
+// matrix-core product.
 //
 // MT = false (a launch-shape variant): KP = 64 with the panels' updates on the
 // vector units up to the end of their 32-column half, and only A22 -= L21

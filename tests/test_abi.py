@@ -205,6 +205,9 @@ def test_autotune_cost_model():
     flat = [np.full(100000, 150)]
     assert not autotune.heavy_split_pays(flat, a, b)
     assert autotune.heavy_split_pays([np.concatenate([np.full(1000, 3), [9000]])], a, b)
+    # a fit that is not a cost (negative per-rating or per-row part) prunes nothing
+    assert autotune.heavy_split_pays(flat, 0.0167, -4.3e-5)
+    assert autotune.heavy_split_pays(flat, -0.001, 1.4e-5)
     info = {"heavy_rows": (1, 0), "rank1_rows": (2, 0), "pieces": (4, 0)}
     assert autotune.launch_rows([np.array([1, 1, 50, 9000]), np.array([3, 4])], info) == [(5, 9050), (2, 7)]
 
