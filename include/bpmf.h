@@ -164,8 +164,7 @@ bpmf_status bpmf_workspace_size(const bpmf_ratings *R, const bpmf_params *p, int
  * otherwise.  d_ws is the caller's workspace of ws_bytes.  n_test held-out
  * pairs (d_test_rows, d_test_cols, int32, device) get a running mean of their
  * predictions over sweeps >= burnin.  Errors: BPMF_E_INVALID (shapes, ranges,
- * CSR/CSC structure when validate = 1; BPMF_BF16 with K <= 64 also needs
- * M, N < 2^24), BPMF_E_NOT_SPD (W0),
+ * CSR/CSC structure when validate = 1; BPMF_BF16 also needs M, N < 2^24), BPMF_E_NOT_SPD (W0),
  * BPMF_E_WORKSPACE, BPMF_E_HIP.  Synchronises `stream` before returning. */
 bpmf_status bpmf_init(bpmf_ctx **ctx, const bpmf_ratings *R, const bpmf_params *p, void *d_U,
                       void *d_V, void *d_ws, size_t ws_bytes, int64_t n_test,

@@ -234,9 +234,9 @@ static bpmf_status check_params(const bpmf_ratings *R, const bpmf_params *p)
     }
     if (R->M < 1 || R->N < 1 || R->nnz < 0) return fail(BPMF_E_INVALID, "M, N must be >= 1, nnz >= 0");
     if (R->M > INT32_MAX || R->N > INT32_MAX) return fail(BPMF_E_INVALID, "M and N must fit in int32");
-    // the K <= 64 BF16 gathers address rows with 32-bit byte offsets
-    if (p->precision == BPMF_BF16 && p->K <= 64 && (R->M >= (1 << 24) || R->N >= (1 << 24)))
-        return fail(BPMF_E_INVALID, "BF16 precision with K <= 64 needs M and N below 2^24");
+    // the BF16 gathers address rows with 32-bit byte offsets
+    if (p->precision == BPMF_BF16 && (R->M >= (1 << 24) || R->N >= (1 << 24)))
+        return fail(BPMF_E_INVALID, "BF16 precision needs M and N below 2^24");
     if (!R->d_row_ptr || !R->d_col_ptr) return fail(BPMF_E_INVALID, "NULL row_ptr/col_ptr");
     if (R->nnz > 0 && (!R->d_col_idx || !R->d_row_val || !R->d_row_idx || !R->d_col_val))
         return fail(BPMF_E_INVALID, "NULL index or value array");

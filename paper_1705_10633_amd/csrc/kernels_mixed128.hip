@@ -15,12 +15,14 @@
 //    row stride 128); chunks of 64 ratings are staged feature-major in LDS;
 //  * Gram: the ten lower 32 x 32 tiles on v_mfma_f32_32x32x16_bf16, three,
 //    three, two and two tiles on the four wavefronts; the right-hand side on
-//    v_dot2c_f32_bf16 (threads 0..127, one feature each);
-//  * wavefront 0 factors P11 with the 64-wide row-per-lane Cholesky and does
-//    the forward solve of block 1, while wavefront 1 solves for L21 (a row
-//    per lane) one 8-column panel behind it; wavefronts 1..3 form one tile
-//    each of L21 L21^T on FP32 matrix cores; wavefront 2 factors the updated
-//    P22 and solves block 2; wavefront 0 finishes block 1.
+//    v_mfma_f32_16x16x32_bf16, 32 features per wavefront;
+//  * wavefront 0 factors P11 with the 64-wide row-per-lane Cholesky and
+//    carries the forward solve of block 1 along, panel by panel; wavefront 1
+//    solves for L21 (a row per lane) one 8-column panel behind it, and
+//    wavefronts 2 and 3 accumulate L21 L21^T on FP32 matrix cores one more
+//    panel behind; wavefront 2 then factors the updated P22 with the forward
+//    solve of block 2 carried along, and solves back; wavefront 0 finishes
+//    block 1.
 //  * a row whose pivot is not finite or not above 64 K 2^-24 max_k P_kk is
 //    not written; it is appended to the FP64 recompute list.
 #include "common.hpp"
@@ -61,16 +63,18 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     DevState *state, int side)
 {
     __shared__ __attribute__((aligned(16))) float u[U2];     // staging, then P (packed), then L11 / L21 in place
-    // panel buffer of the two 64-wide factorisations (never at the same time)
-    __shared__ __attribute__((aligned(16))) float pb[H2 * 12];
     __shared__ __attribute__((aligned(16))) float bvec[K2], zvec[K2];
     __shared__ __attribute__((aligned(16))) float y1[H2], b2[H2], x2v[H2], inv11[H2], inv22[H2], yb2[H2],
         xb2[H2], xb0[H2];
-    __shared__ __attribute__((aligned(16))) uint32_t rvp[CH2];
+    // hi pairs, lo pairs, zero words of the chunk's r' (the right-hand side's A operand)
+    __shared__ __attribute__((aligned(16))) uint32_t rvp[3 * CH2 / 2];
     __shared__ float red[4];
     __shared__ int fails[2];
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wavefront index in a scalar register: the branches on it are uniform,
+    // so the barriers inside them are executed by whole wavefronts
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int4 rt = sa.rowtab[blockIdx.x];
     const int row = rt.x;
     const int64_t nnz = rt.y;
@@ -85,15 +89,28 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     for (int t = 0; t < 3; ++t)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
-    float bacc = 0.0f;
+    // right-hand side: wavefront w collects features 32 w .. 32 w + 31 as two
+    // 16-feature groups on v_mfma_f32_16x16x32_bf16 (A: row 0 the hi parts of
+    // 32 ratings, row 1 their lo parts, rows 2..15 zero; B: the staged features)
+    floatx4 bq[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bq[g][e] = 0.0f;
+    if (tid < CH2 / 2) rvp[CH2 + tid] = 0u;
+    const uint4 *aop = (const uint4 *)(rvp + (lane % 16 < 2 ? lane % 16 : 2) * (CH2 / 2)) + lane / 16;
     char *stage = (char *)u;
     const int fb = tid / RG2, rg = tid % RG2;
     static_assert(CH2 == bf16_chunk(K2), "records are padded to the kernel's chunk");
+    // 32-bit byte offsets from the uniform base (the host keeps each side
+    // below 2^24 rows): one multiply-add per load
+    const char *base = (const char *)src;
+    const uint32_t fbb = 16u * (uint32_t)fb;
     auto load_rows = [&](const uint4 &c, uint4 *d) {
-        d[0] = *(const uint4 *)(src + (int64_t)(int)c.x * K2 + fb * 8);
-        d[1] = *(const uint4 *)(src + (int64_t)(int)c.y * K2 + fb * 8);
-        d[2] = *(const uint4 *)(src + (int64_t)(int)c.z * K2 + fb * 8);
-        d[3] = *(const uint4 *)(src + (int64_t)(int)c.w * K2 + fb * 8);
+        d[0] = *(const uint4 *)(base + (__umul24(c.x, 2u * K2) + fbb));
+        d[1] = *(const uint4 *)(base + (__umul24(c.y, 2u * K2) + fbb));
+        d[2] = *(const uint4 *)(base + (__umul24(c.z, 2u * K2) + fbb));
+        d[3] = *(const uint4 *)(base + (__umul24(c.w, 2u * K2) + fbb));
     };
     auto stage_chunk = [&](const uint4 *d, const uint4 &rp) {
         if (fb == 0) {
@@ -108,10 +125,10 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         for (int w = 0; w < 4; ++w) {
             const int f = fb * 8 + 2 * w;
             uint2 lo, hi;
-            lo.x = (w0[w] & 0xffffu) | (w1[w] << 16);
-            lo.y = (w2[w] & 0xffffu) | (w3[w] << 16);
-            hi.x = (w0[w] >> 16) | (w1[w] & 0xffff0000u);
-            hi.y = (w2[w] >> 16) | (w3[w] & 0xffff0000u);
+            lo.x = __builtin_amdgcn_perm(w1[w], w0[w], 0x05040100u);
+            lo.y = __builtin_amdgcn_perm(w3[w], w2[w], 0x05040100u);
+            hi.x = __builtin_amdgcn_perm(w1[w], w0[w], 0x07060302u);
+            hi.y = __builtin_amdgcn_perm(w3[w], w2[w], 0x07060302u);
             *(uint2 *)(stage + f * SB2 + rg * 8) = lo;
             *(uint2 *)(stage + (f + 1) * SB2 + rg * 8) = hi;
         }
@@ -131,24 +148,14 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                 }
             }
         }
-        if (tid < K2) {
-            const uint4 *sp = (const uint4 *)(stage + tid * SB2);
-            const uint4 *hp = (const uint4 *)rvp, *lp = (const uint4 *)(rvp + CH2 / 2);
 #pragma unroll
-            for (int p4 = 0; p4 < CH2 / 8; ++p4) {
-                const uint4 sv = sp[p4], hv = hp[p4], lv = lp[p4];
-                const uint32_t sa4[4] = {sv.x, sv.y, sv.z, sv.w};
-                const uint32_t ha[4] = {hv.x, hv.y, hv.z, hv.w};
-                const uint32_t la[4] = {lv.x, lv.y, lv.z, lv.w};
+        for (int ks = 0; ks < CH2 / 32; ++ks) {
+            const bf16x8_t Ar = *(const bf16x8_t *)(aop + 4 * ks);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    bf16x2_t x, yh, yl;
-                    __builtin_memcpy(&x, &sa4[q], 4);
-                    __builtin_memcpy(&yh, &ha[q], 4);
-                    __builtin_memcpy(&yl, &la[q], 4);
-                    bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yh, bacc, false);
-                    bacc = __builtin_amdgcn_fdot2_f32_bf16(x, yl, bacc, false);
-                }
+            for (int g = 0; g < 2; ++g) {
+                const int f = 32 * wave + 16 * g + lane % 16;
+                const bf16x8_t Bf = *(const bf16x8_t *)(stage + f * SB2 + (ks * 32 + (lane / 16) * 8) * 2);
+                bq[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Bf, bq[g], 0, 0, 0);
             }
         }
     };
@@ -202,8 +209,14 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                 }
         }
     }
-    if (tid < K2) {
-        bvec[tid] = fmaf(alpha, bacc, hyp.Lmu_f[tid < K ? tid : 0]) * (tid < K ? 1.0f : 0.0f);
+    {
+        // lane c < 16 of bq[g] holds the hi (element 0) and lo (element 1)
+        // sums of feature 32 wave + 16 g + c
+        const float v0 = __shfl(bq[0][0] + bq[0][1], lane % 16), v1 = __shfl(bq[1][0] + bq[1][1], lane % 16);
+        if (lane < 32) {
+            const int f = 32 * wave + lane;
+            bvec[f] = fmaf(alpha, lane < 16 ? v0 : v1, hyp.Lmu_f[f < K ? f : 0]) * (f < K ? 1.0f : 0.0f);
+        }
     }
     if (draws.tape_rows) {
         if (tid < K2) zvec[tid] = tid < K ? (float)draws.tape_rows[(int64_t)row * K + (tid < K ? tid : 0)] : 0.0f;
@@ -226,119 +239,149 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     __syncthreads();
     const float tau = 64.0f * (float)K * 0x1.0p-24f * fmaxf(red[0], red[1]);
 
-    // ---------------- block 1: L11 (wavefront 0) and L21 (wavefront 1), panel by panel ----------------
-    // Wavefront 0 factors P11 with the 64-wide row-per-lane Cholesky in eight
-    // steps of 8 columns; after step p it publishes the panel's columns of
-    // L11 into the packed triangle (over P11, lower part only: entries right
-    // of a row's diagonal would land in the next rows' slots).  Wavefront 1
-    // keeps row r of P21 in registers and, one step behind, solves the same 8
-    // columns of L21 = P21 L11^{-T} right-looking: x_k = a_k / L11_kk, then
-    // a_j -= x_k L11_jk for the later columns.  Every thread passes the same
-    // barriers; only the work between them differs by wavefront.
-    float A[H2];
-    if (wave == 0) {
-#pragma unroll
-        for (int c = 0; c < H2; ++c) A[c] = P[rowoff(lane) + c];
-    } else if (wave == 1) {
-#pragma unroll
-        for (int c = 0; c < H2; ++c) A[c] = P[rowoff(H2 + lane) + c];
-    }
-    auto publish = [&](int c0) {
+    // ---------------- block 1 and P22 - L21 L21^T, panel by panel ----------------
+    // Eight steps of 8 columns; at each step, on its own wavefront:
+    //  * wavefront 0 factors the panel of P11 with the 64-wide row-per-lane
+    //    Cholesky, publishes its columns of L11 into the packed triangle (over
+    //    P11, lower part only) and carries the forward solve y1 = L11^{-1} b1
+    //    over the panel (y_k = t_k / L_kk, then t -= L[:, k] y_k);
+    //  * wavefront 1, one step behind, solves the same columns of
+    //    L21 = P21 L11^{-T} right-looking from the published panel, carries
+    //    b2 - L21 y1 over them and publishes them over P21;
+    //  * wavefronts 2 and 3, one more step behind, accumulate the panel's
+    //    rank-8 part of L21 L21^T on FP32 matrix cores (wavefront 2 the
+    //    diagonal tiles, wavefront 3 the off-diagonal one).
+    // The branch on the wavefront is uniform and every path passes the same
+    // ten barriers.
+    auto publish = [&](const float (&A)[H2], int c0) {
 #pragma unroll
         for (int c = c0; c < c0 + 8; ++c)
             if (c <= lane) P[rowoff(lane) + c] = A[c];
     };
-    auto trsm_panel = [&](int c0) {
+    // forward solve over columns c0..c0+7 of the factored rows in A
+    auto fwd_panel = [&](const float (&A)[H2], float &t, const float *inv, float *ybuf, int c0) {
 #pragma unroll
         for (int k = c0; k < c0 + 8; ++k) {
-            const float x = A[k] * inv11[k];
-            A[k] = x;
-#pragma unroll
-            for (int j = k + 1; j < c0 + 8; ++j) A[j] = fmaf(-x, P[rowoff(j) + k], A[j]);
-        }
-#pragma unroll
-        for (int j = c0 + 8; j < H2; ++j) {
-            const float *lj = P + rowoff(j) + c0;
-            float t = A[j];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) t = fmaf(-A[c0 + k], lj[k], t);
-            A[j] = t;
+            const float yk = readlane_f(t, k) * inv[k];
+            ybuf[k] = yk;
+            t = fmaf(-A[k], yk, t);
         }
     };
-#define BLOCK1_STEP(Q)                                                   \
-    if (wave == 0) {                                                     \
-        chol64_step<Q, WaveSync>(A, inv11, pb);                          \
-        publish(8 * (Q));                                                \
-    }                                                                    \
-    __syncthreads();                                                     \
-    if (wave == 1) trsm_panel(8 * (Q));
-    BLOCK1_STEP(0)
-    BLOCK1_STEP(1)
-    BLOCK1_STEP(2)
-    BLOCK1_STEP(3)
-    BLOCK1_STEP(4)
-    BLOCK1_STEP(5)
-    BLOCK1_STEP(6)
-    BLOCK1_STEP(7)
-#undef BLOCK1_STEP
     if (wave == 0) {
-        const float iv = inv11[lane];
-        const bool f0 = chol_pivots_fail(iv, lane, K < H2 ? K : H2, tau);
+        float A[H2];
+#pragma unroll
+        for (int c = 0; c < H2; ++c) A[c] = P[rowoff(lane) + c];
+        float t = bvec[lane];
+#define W0_STEP(Q)                                   \
+    chol64_step<Q, WaveSync>(A, inv11);              \
+    publish(A, 8 * (Q));                             \
+    fwd_panel(A, t, inv11, y1, 8 * (Q));             \
+    __syncthreads();
+        W0_STEP(0) W0_STEP(1) W0_STEP(2) W0_STEP(3) W0_STEP(4) W0_STEP(5) W0_STEP(6) W0_STEP(7)
+#undef W0_STEP
+        const bool f0 = chol_pivots_fail(inv11[lane], lane, K < H2 ? K : H2, tau);
         if (lane == 0) fails[0] = f0 ? 1 : 0;
-        forward_sub<H2, WaveSync>(A, iv, bvec[lane], y1);
-    }
-    __syncthreads();
-
-    // ---------------- b2 - L21 y1 and L21 into LDS (wavefront 1) ----------------
-    if (wave == 1) {
+        __syncthreads();
+        __syncthreads();
+    } else if (wave == 1) {
+        float A[H2];
+#pragma unroll
+        for (int c = 0; c < H2; ++c) A[c] = P[rowoff(H2 + lane) + c];
         float t = bvec[H2 + lane];
+        auto trsm_panel = [&](int c0) {
 #pragma unroll
-        for (int k = 0; k < H2; ++k) t = fmaf(-A[k], y1[k], t);
+            for (int k = c0; k < c0 + 8; ++k) {
+                const float x = A[k] * inv11[k];
+                A[k] = x;
+#pragma unroll
+                for (int j = k + 1; j < c0 + 8; ++j) A[j] = fmaf(-x, P[rowoff(j) + k], A[j]);
+            }
+#pragma unroll
+            for (int j = c0 + 8; j < H2; ++j) {
+                const float *lj = P + rowoff(j) + c0;
+                float u = A[j];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) u = fmaf(-A[c0 + k], lj[k], u);
+                A[j] = u;
+            }
+#pragma unroll
+            for (int k = c0; k < c0 + 8; ++k) {
+                t = fmaf(-A[k], y1[k], t);
+                P[rowoff(H2 + lane) + k] = A[k];
+            }
+        };
+#define W1_STEP(Q)   \
+    __syncthreads(); \
+    trsm_panel(8 * (Q));
+        W1_STEP(0) W1_STEP(1) W1_STEP(2) W1_STEP(3) W1_STEP(4) W1_STEP(5) W1_STEP(6) W1_STEP(7)
+#undef W1_STEP
         b2[lane] = t;
-        // L21 over P21 (the operands of L21 L21^T, then the block-1 back substitution)
+        __syncthreads();
+        __syncthreads();
+    } else {
+        // wavefront 2: tiles (0, 0) and (1, 1) of C = L21 L21^T; wavefront 3:
+        // tile (1, 0).  Operand lane l holds L21[32 a + l % 32][k + l / 32]
+        // (read from the published panels); result element 4j + i of lane l
+        // is C[32 a + 8j + 4(l / 32) + i][32 b + l % 32].
+        const bool w2 = wave == 2;
+        const float *r0 = P + rowoff(H2 + (lane & 31)) + (lane >> 5);
+        const float *r1 = P + rowoff(H2 + 32 + (lane & 31)) + (lane >> 5);
+        floatx16 c0 = {}, c1 = {};
+        auto syrk_panel = [&](int k0) {
 #pragma unroll
-        for (int c = 0; c < H2; ++c) P[rowoff(H2 + lane) + c] = A[c];
-    }
-    __syncthreads();
-
-    // ---------------- P22 -= L21 L21^T: one 32 x 32 tile per wavefront 1..3 ----------------
-    // Tile (a, b) of C = L21 L21^T (a, b in {0, 1}: rows 0-31 / 32-63 of L21)
-    // in 32 rank-2 steps of v_mfma_f32_32x32x2_f32; operand lane l holds
-    // L21[32 a + l % 32][2 kk + l / 32], read from LDS.  Result element
-    // v = 4j + i of lane l is C[32 a + 8j + 4(l / 32) + i][32 b + l % 32].
-    if (wave >= 1) {
-        const int ta = wave == 1 ? 0 : 1, tb = wave == 3 ? 1 : 0;
-        const float *ra = P + rowoff(H2 + 32 * ta + (lane & 31)) + (lane >> 5);
-        const float *rb = P + rowoff(H2 + 32 * tb + (lane & 31)) + (lane >> 5);
-        floatx16 c = {};
-#pragma unroll
-        for (int kk = 0; kk < H2 / 2; ++kk) {
-            const float xa = ra[2 * kk], xb = rb[2 * kk];
-            c = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xb, c, 0, 0, 0);
-        }
+            for (int kk = 0; kk < 4; ++kk) {
+                const float x0 = r0[k0 + 2 * kk], x1 = r1[k0 + 2 * kk];
+                if (w2) {
+                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x0, x0, c0, 0, 0, 0);
+                    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x1, x1, c1, 0, 0, 0);
+                } else {
+                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x1, x0, c0, 0, 0, 0);
+                }
+            }
+        };
+#define W23_STEP(Q)                          \
+    __syncthreads();                         \
+    if ((Q) >= 1) syrk_panel(8 * ((Q) - 1));
+        W23_STEP(0) W23_STEP(1) W23_STEP(2) W23_STEP(3) W23_STEP(4) W23_STEP(5) W23_STEP(6) W23_STEP(7)
+#undef W23_STEP
+        __syncthreads();
+        syrk_panel(56);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int m = 32 * ta + 8 * j + 4 * (lane >> 5) + i, n = 32 * tb + (lane & 31);
-                if (n <= m) P[rowoff(H2 + m) + H2 + n] -= c[4 * j + i];
+                const int m = 8 * j + 4 * (lane >> 5) + i, n = lane & 31;
+                if (w2) {
+                    if (n <= m) {
+                        P[rowoff(H2 + m) + H2 + n] -= c0[4 * j + i];
+                        P[rowoff(H2 + 32 + m) + H2 + 32 + n] -= c1[4 * j + i];
+                    }
+                } else {
+                    P[rowoff(H2 + 32 + m) + H2 + n] -= c0[4 * j + i];
+                }
             }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---------------- block 2: L22, y2, x2 (wavefront 2) ----------------
     if (wave == 2) {
+        float A[H2];
 #pragma unroll
         for (int c = 0; c < H2; ++c) A[c] = P[rowoff(H2 + lane) + H2 + c];
+        float t = b2[lane];
         WaveSync::sync();
-        chol_factor<H2, WaveSync>(A, inv22, pb);
+#define W2_STEP(Q)                     \
+    chol64_step<Q, WaveSync>(A, inv22); \
+    fwd_panel(A, t, inv22, yb2, 8 * (Q));
+        W2_STEP(0) W2_STEP(1) W2_STEP(2) W2_STEP(3) W2_STEP(4) W2_STEP(5) W2_STEP(6) W2_STEP(7)
+#undef W2_STEP
         const float iv = inv22[lane];
         const bool f2 = chol_pivots_fail(iv, lane, K - H2, tau);
         if (lane == 0) fails[1] = f2 ? 1 : 0;
-        const float y = forward_sub<H2, WaveSync>(A, iv, b2[lane], yb2);
         // masked: past its diagonal a row would run into the next row's L21
         store_rows_lower<H2, H2>(A, P + P22OFF);
         WaveSync::sync();
+        const float y = yb2[lane];
         x2v[lane] = backward_sub<H2, WaveSync, H2>(P + P22OFF, iv, y + zvec[H2 + lane], xb2);
     }
     __syncthreads();

@@ -479,7 +479,7 @@ __device__ __forceinline__ void chol_panel(float (&A)[KP], float *invbuf, float 
 // columns (the updates by the earlier panels that are still pending) and the
 // panel itself.  After step P, lane ri holds its final L[ri][8P..8P+7].
 template <int P, class Sync>
-__device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf, float *pbuf)
+__device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf)
 {
     if constexpr (P == 1 || P == 3 || P == 5 || P == 7) next8_mfma<8 * (P - 1), 8 * P>(A);
     if constexpr (P == 2) gemm_cols16_31(A);
@@ -519,14 +519,14 @@ __device__ __forceinline__ void chol_factor(float (&A)[KP], float *invbuf, float
             if (c0 == 24) syrk_lower_rows<0, 32, 0>(A);
         }
     } else if constexpr (KP == 64) {
-        chol64_step<0, Sync>(A, invbuf, pbuf);
-        chol64_step<1, Sync>(A, invbuf, pbuf);
-        chol64_step<2, Sync>(A, invbuf, pbuf);
-        chol64_step<3, Sync>(A, invbuf, pbuf);
-        chol64_step<4, Sync>(A, invbuf, pbuf);
-        chol64_step<5, Sync>(A, invbuf, pbuf);
-        chol64_step<6, Sync>(A, invbuf, pbuf);
-        chol64_step<7, Sync>(A, invbuf, pbuf);
+        chol64_step<0, Sync>(A, invbuf);
+        chol64_step<1, Sync>(A, invbuf);
+        chol64_step<2, Sync>(A, invbuf);
+        chol64_step<3, Sync>(A, invbuf);
+        chol64_step<4, Sync>(A, invbuf);
+        chol64_step<5, Sync>(A, invbuf);
+        chol64_step<6, Sync>(A, invbuf);
+        chol64_step<7, Sync>(A, invbuf);
     } else {
 #pragma unroll
         for (int c0 = 0; c0 < KP; c0 += 8) chol_panel<KP, Sync>(A, invbuf, pbuf, c0, KP);

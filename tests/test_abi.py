@@ -116,7 +116,7 @@ def test_workspace_size_validates_parameters(lib):
     from paper_1705_10633_amd import _lib
     nulls = _lib.Ratings(10, 8, 20, 0x1000, None, None, 0x1000, None, None, 0)
     assert _ws(lib, nulls, p)[0] == 1
-    # BF16 at K <= 64 addresses gathered rows with 32-bit offsets: sides below 2^24 rows
+    # BF16 addresses gathered rows with 32-bit offsets: sides below 2^24 rows
     big = _ratings(M=1 << 24)
     p, keep = _params(precision=2)
     assert _ws(lib, big, p)[0] == 1 and b"2^24" in lib.bpmf_last_error()
