@@ -63,6 +63,8 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     DevState *state, int side)
 {
     __shared__ __attribute__((aligned(16))) float u[U2];     // staging, then P (packed), then L11 / L21 in place
+    // panel buffer of the two 64-wide factorisations (never at the same time)
+    __shared__ __attribute__((aligned(16))) float pb[H2 * 12];
     __shared__ __attribute__((aligned(16))) float bvec[K2], zvec[K2];
     __shared__ __attribute__((aligned(16))) float y1[H2], b2[H2], x2v[H2], inv11[H2], inv22[H2], yb2[H2],
         xb2[H2], xb0[H2];
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         for (int c = 0; c < H2; ++c) A[c] = P[rowoff(lane) + c];
         float t = bvec[lane];
 #define W0_STEP(Q)                                   \
-    chol64_step<Q, WaveSync>(A, inv11);              \
+    chol64_step<Q, WaveSync>(A, inv11, pb);              \
     publish(A, 8 * (Q));                             \
     fwd_panel(A, t, inv11, y1, 8 * (Q));             \
     __syncthreads();
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         float t = b2[lane];
         WaveSync::sync();
 #define W2_STEP(Q)                     \
-    chol64_step<Q, WaveSync>(A, inv22); \
+    chol64_step<Q, WaveSync>(A, inv22, pb); \
     fwd_panel(A, t, inv22, yb2, 8 * (Q));
         W2_STEP(0) W2_STEP(1) W2_STEP(2) W2_STEP(3) W2_STEP(4) W2_STEP(5) W2_STEP(6) W2_STEP(7)
 #undef W2_STEP

@@ -368,54 +368,6 @@ __device__ __forceinline__ void gemm_cols16_31(float *A)
         }
 }
 
-// Columns C0..C0+7 from the factored panel K0..K0+7 (K0 + 8 = C0), on the
-// matrix cores: A[r][c] -= sum_{k in K0..K0+7} L[r][k] L[c][k].  C0 < 32: for
-// all 64 rows as in gemm_cols16_31 (D0 for rows 0..31, D1 for rows 32..63);
-// C0 >= 32: for rows 32..63 as in syrk_lower_rows (rows 0..31 have no entries
-// there left of their diagonal).
-template <int K0, int C0>
-__device__ __forceinline__ void next8_mfma(float *A)
-{
-    static_assert(K0 + 8 == C0 && C0 % 8 == 0 && C0 < 64, "next panel of a factored panel");
-    if constexpr (C0 < 32) {
-        floatx16 d0 = {}, d1 = {};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[K0 + 2 * kk]),
-                                                             __float_as_uint(A[K0 + 2 * kk + 1]), false, false);
-            const float xa = __uint_as_float(sw[0]), xb = __uint_as_float(sw[1]);
-            d0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xa, d0, 0, 0, 0);
-            d1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xb, d1, 0, 0, 0);
-        }
-        constexpr int j = C0 / 8;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(d0[4 * j + i]),
-                                                             __float_as_uint(d1[4 * j + i]), false, false);
-            A[8 * j + i] -= __uint_as_float(sw[0]);
-            A[8 * j + 4 + i] -= __uint_as_float(sw[1]);
-        }
-    } else {
-        floatx16 c = {};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(A[K0 + 2 * kk]),
-                                                             __float_as_uint(A[K0 + 2 * kk + 1]), false, false);
-            const float x = __uint_as_float(sw[1]);
-            c = __builtin_amdgcn_mfma_f32_32x32x2f32(x, x, c, 0, 0, 0);
-        }
-        constexpr int j = (C0 - 32) / 8;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float own = c[4 * j + i];
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(own), __float_as_uint(own),
-                                                             false, false);
-            A[32 + 8 * j + 4 + i] -= own;
-            A[32 + 8 * j + i] -= __uint_as_float(sw[0]);
-        }
-    }
-}
-
 // Columns c0..c0+7 of the matrix whose row ri = lane % KP is in A: column k
 // is scaled by 1/sqrt(P_kk) (lane k thereby holds L_kk, invbuf[k] = 1/L_kk)
 // and the later panel columns are updated with values read across lanes with
@@ -479,9 +431,9 @@ __device__ __forceinline__ void chol_panel(float (&A)[KP], float *invbuf, float 
 // columns (the updates by the earlier panels that are still pending) and the
 // panel itself.  After step P, lane ri holds its final L[ri][8P..8P+7].
 template <int P, class Sync>
-__device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf)
+__device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf, float *pbuf)
 {
-    if constexpr (P == 1 || P == 3 || P == 5 || P == 7) next8_mfma<8 * (P - 1), 8 * P>(A);
+    if constexpr (P == 1 || P == 3 || P == 5 || P == 7) chol_next<64, Sync>(A, pbuf, 8 * (P - 1), 8 * (P + 1));
     if constexpr (P == 2) gemm_cols16_31(A);
     if constexpr (P == 4) syrk_lower_rows<0, 32, 0>(A);
     if constexpr (P == 6) syrk_lower_rows<32, 16, 2>(A);
@@ -497,14 +449,16 @@ __device__ __forceinline__ void chol64_step(float (&A)[64], float *invbuf)
 // masks.  An unusable pivot gives a NaN, infinite or zero 1/sqrt, caught by
 // chol_pivots_fail.
 //
-// KP = 64: every update beyond a panel's own 8 columns is a matrix-core
-// product: the next panel from the one just factored (next8_mfma), columns
-// 16..31 of all rows from columns 0..15 (gemm_cols16_31), the trailing
-// 32 x 32 block A22 -= L21 L21^T from columns 0..31, and columns 48..63 of
-// rows 32..63 from columns 32..47 (syrk_lower_rows).  That leaves the 224
-// multiply-add instructions per lane inside the panels on the vector units,
-// against 480 with the next-panel updates there and 992 when only A22 was a
-// matrix-core product.
+// KP = 64: the panels' updates reach only the next panel of their 16-column
+// block on the vector units; everything further right is a matrix-core
+// product: columns 16..31 of all rows from columns 0..15 (gemm_cols16_31),
+// the trailing 32 x 32 block A22 -= L21 L21^T from columns 0..31, and
+// columns 48..63 of rows 32..63 from columns 32..47 (syrk_lower_rows).
+// That leaves 480 multiply-add instructions per lane on the vector units (224
+// inside the panels, 256 for the next panel), against 992 when only A22 was
+// a matrix-core product.  (The next-panel updates on the matrix cores too
+// measured neutral in the sampler and 15 % slower in the fold-in kernel,
+// where many more wavefronts share the matrix cores.)
 //
 // MT = false (a launch-shape variant): KP = 64 with the panels' updates on the
 // vector units up to the end of their 32-column half, and only A22 -= L21
@@ -519,14 +473,14 @@ __device__ __forceinline__ void chol_factor(float (&A)[KP], float *invbuf, float
             if (c0 == 24) syrk_lower_rows<0, 32, 0>(A);
         }
     } else if constexpr (KP == 64) {
-        chol64_step<0, Sync>(A, invbuf);
-        chol64_step<1, Sync>(A, invbuf);
-        chol64_step<2, Sync>(A, invbuf);
-        chol64_step<3, Sync>(A, invbuf);
-        chol64_step<4, Sync>(A, invbuf);
-        chol64_step<5, Sync>(A, invbuf);
-        chol64_step<6, Sync>(A, invbuf);
-        chol64_step<7, Sync>(A, invbuf);
+        chol64_step<0, Sync>(A, invbuf, pbuf);
+        chol64_step<1, Sync>(A, invbuf, pbuf);
+        chol64_step<2, Sync>(A, invbuf, pbuf);
+        chol64_step<3, Sync>(A, invbuf, pbuf);
+        chol64_step<4, Sync>(A, invbuf, pbuf);
+        chol64_step<5, Sync>(A, invbuf, pbuf);
+        chol64_step<6, Sync>(A, invbuf, pbuf);
+        chol64_step<7, Sync>(A, invbuf, pbuf);
     } else {
 #pragma unroll
         for (int c0 = 0; c0 < KP; c0 += 8) chol_panel<KP, Sync>(A, invbuf, pbuf, c0, KP);
