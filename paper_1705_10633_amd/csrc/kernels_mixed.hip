@@ -49,15 +49,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
     const int lane = threadIdx.x;
     const float *vals = (const float *)a.val;
 
+    // gram_bf16 starts the accumulators itself; the other paths clear them
     floatx16 acc[S::NTILE];
-#pragma unroll
-    for (int t = 0; t < S::NTILE; ++t)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
     float bacc = 0.0f;
+    auto clear_acc = [&]() {
+#pragma unroll
+        for (int t = 0; t < S::NTILE; ++t)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
+    };
 
     int row;
     if (pc.combine) {
+        clear_acc();
         // {row, first piece, piece count, -}
         const int4 ct = pc.ctab[blockIdx.x];
         row = ct.x;
@@ -77,9 +81,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
         if constexpr (BF16)
             gram_bf16<KP>(a.rec + 2 * a.recoff[blockIdx.x], s1 - s0, a.other_bf16, a.shadow_stride, (char *)u,
                           (uint32_t *)rv, acc, bacc);
-        else
+        else {
+            clear_acc();
             gram_f32<KP>(a.idx + s0, vals + s0, s1 - s0, (const float *)a.other, K, rbar, u, rv,
                          sidx, acc, bacc);
+        }
         if (row < 0) {
             float *dst = pc.part + (int64_t)(-row - 1) * PW;
 #pragma unroll

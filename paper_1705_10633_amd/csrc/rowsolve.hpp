@@ -9,6 +9,8 @@
 // The paper's row conditional (Section 2, Algorithm 1) and the choice of a
 // Cholesky factorisation over an inverse (Section 3.1).
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace bpmf {
@@ -76,11 +78,9 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
     static_assert(S::CH % 32 == 0, "the right-hand side takes 32 ratings per step");
     constexpr int NG = KP / 16;   // 16-feature groups of the right-hand side
     const int lane = threadIdx.x & 63;
+    // the accumulators start from the first chunk's products (a zero C
+    // operand, so no register is cleared); a row without ratings clears them
     floatx4 bq[NG];
-#pragma unroll
-    for (int t = 0; t < NG; ++t)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) bq[t][e] = 0.0f;
     // rows 2..15 of the right-hand side's A operand read the zero words
     if (lane < S::CH / 2) rvp[S::CH + lane] = 0u;
     const uint4 *aop = (const uint4 *)(rvp + (lane % 16 < 2 ? lane % 16 : 2) * (S::CH / 2)) + lane / 16;
@@ -124,17 +124,22 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
             *(uint2 *)(stage + (f + 1) * S::SB + rg * 8) = hi;
         }
     };
-    // Gram tiles and right-hand side of the staged chunk
-    auto multiply_chunk = [&]() {
+    // Gram tiles and right-hand side of the staged chunk (the first chunk
+    // starts every accumulator from zero)
+    const floatx16 zero16 = {};
+    const floatx4 zero4 = {};
+    auto multiply_chunk = [&](auto first_chunk) {
+        constexpr bool FIRST = decltype(first_chunk)::value;
 #pragma unroll
         for (int ks = 0; ks < S::CH / 16; ++ks) {
             const int off = (ks * 16 + (lane >> 5) * 8) * 2;
+            const bool fresh = FIRST && ks == 0;
             const bf16x8_t F0 = *(const bf16x8_t *)(stage + (lane & 31) * S::SB + off);
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F0, F0, acc[0], 0, 0, 0);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F0, F0, fresh ? zero16 : acc[0], 0, 0, 0);
             if constexpr (KP == 64) {
                 const bf16x8_t F1 = *(const bf16x8_t *)(stage + (32 + (lane & 31)) * S::SB + off);
-                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F0, acc[1], 0, 0, 0);
-                acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, acc[2], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F0, fresh ? zero16 : acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, fresh ? zero16 : acc[2], 0, 0, 0);
             }
         }
 #pragma unroll
@@ -146,7 +151,7 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
                 // B: lane l holds feature 16 t + l % 16 of the same ratings
                 const bf16x8_t Bf =
                     *(const bf16x8_t *)(stage + (16 * t + lane % 16) * S::SB + (ks * 32 + (lane / 16) * 8) * 2);
-                bq[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Bf, bq[t], 0, 0, 0);
+                bq[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Bf, (FIRST && ks == 0) ? zero4 : bq[t], 0, 0, 0);
             }
         }
     };
@@ -176,8 +181,17 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
             }
         }
         Sync::sync();
-        multiply_chunk();
+        if (c == 0)
+            multiply_chunk(std::true_type{});
+        else
+            multiply_chunk(std::false_type{});
         Sync::sync();
+    }
+    if (nch == 0) {
+#pragma unroll
+        for (int t = 0; t < S::NTILE; ++t) acc[t] = zero16;
+#pragma unroll
+        for (int t = 0; t < NG; ++t) bq[t] = zero4;
     }
     // lane c < 16 of bq[t] holds the hi (element 0) and lo (element 1) sums of
     // feature 16 t + c; lane l takes feature l % KP
