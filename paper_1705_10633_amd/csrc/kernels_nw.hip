@@ -25,6 +25,8 @@ namespace bpmf {
 
 namespace {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 // sums[e] = sum over chunks of partials[c][e]: 8 threads per entry over fixed
 // chunk ranges, combined by a fixed xor tree.
 __global__ __launch_bounds__(256) void stats_reduce_kernel(StatsSides ss, double *sums0, double *sums1,
@@ -243,7 +245,7 @@ constexpr int NSUMS = NWK + NWK * (NWK + 1) / 2;  // sum x and packed sum x x^T 
 
 size_t nw_compact_lds_bytes()
 {
-    return sizeof(double) * ((size_t)2 * NWK * NCS + 10 * NWK + NSUMS);
+    return sizeof(double) * ((size_t)2 * NWK * NCS + 11 * NWK + NSUMS);
 }
 
 __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide side1, int K,
@@ -256,7 +258,8 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     double *xbar = Tm + NWK * NCS;
     double *chi2 = xbar + NWK, *zm = chi2 + NWK, *vinv = zm + NWK, *dvec = vinv + NWK, *mul = dvec + NWK;
     double *lpart = mul + NWK;         // 4 x 64 partial sums of Lambda mu
-    double *sl = lpart + 4 * NWK;      // the side's sums, copied once
+    double *mu0s = lpart + 4 * NWK;    // the prior mean
+    double *sl = mu0s + NWK;           // the side's sums, copied once
     __shared__ int s_flag;
     const NwSide &sd = blockIdx.x == 0 ? side0 : side1;
     const double *sums = sd.sums;
@@ -265,68 +268,70 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     const HyperDev hyp = sd.hyp;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NB = K * (K - 1) / 2;
-    const double dn = (double)n, bstar = beta0 + dn, nstar = nu0 + dn;
+    const double dn = (double)n, bstar = beta0 + dn;
 
+    // Every global read of the side is issued first, together: the sums, the
+    // prior's W0^{-1} (16 entries per thread, kept in registers), mu0 and the
+    // draws (chi^2 of the Bartlett diagonal, its strict lower part in row-major
+    // order q = r (r - 1) / 2 + c, the mean normals; at K <= 64 they always
+    // come as a tape, drawn by the statistics launch when the sampler draws on
+    // the device).  A = Tm is written whole: the draws below the diagonal,
+    // sqrt(chi^2) on it, the identity in the padding and zeros above.
     if (tid == 0) s_flag = 0;
-    for (int e = tid; e < NWK * NCS; e += 256) Tm[e] = 0.0;
-    for (int e = tid; e < K + K * (K + 1) / 2; e += 256) sl[e] = sums[e];
+    const double *tape = draws.tape_nw;
+    double w0r[NWK * NWK / 256];
+#pragma unroll
+    for (int u = 0; u < NWK * NWK / 256; ++u) {
+        const int e = tid + 256 * u, i = e >> 6, j = e & 63;
+        const bool in = i < K && j < K;
+        w0r[u] = W0inv[in ? i * K + j : 0] * (in ? 1.0 : 0.0);
+    }
+    constexpr int SU = (NSUMS + 255) / 256;
+    const int E = K + K * (K + 1) / 2;
+    double sv[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) sv[u] = sums[min(tid + 256 * u, E - 1)];
+    // (all loads first, unconditionally, so none waits behind a branch)
+    double tv[NWK * NWK / 256];
+#pragma unroll
+    for (int u = 0; u < NWK * NWK / 256; ++u) {
+        const int e = tid + 256 * u, r = e >> 6, c = e & 63;
+        tv[u] = tape[(r < K && c < r) ? K + r * (r - 1) / 2 + c : 0];
+    }
+    const int kk = tid < K ? tid : 0;
+    const double chi = tape[kk], zq = tape[K + NB + kk], m0 = mu0[kk];
+#pragma unroll
+    for (int u = 0; u < SU; ++u)
+        if (tid + 256 * u < E) sl[tid + 256 * u] = sv[u];
+    if (tid < K) {
+        mu0s[tid] = m0;
+        zm[tid] = zq;
+    }
+#pragma unroll
+    for (int u = 0; u < NWK * NWK / 256; ++u) {
+        const int e = tid + 256 * u, r = e >> 6, c = e & 63;
+        if (!(r < K && c == r)) Tm[r * NCS + c] = (r < K && c < r) ? tv[u] : (c == r ? 1.0 : 0.0);
+    }
+    if (tid < K) Tm[tid * NCS + tid] = sqrt(chi);
     __syncthreads();
     for (int a = tid; a < NWK; a += 256) xbar[a] = (a < K && n > 0) ? sl[a] / dn : 0.0;
-    // draws: chi^2 of the Bartlett diagonal, the strict lower part of A (row-
-    // major order q = r (r - 1) / 2 + c) straight into Tm, the mean normals
-    if (draws.tape_nw) {
-        for (int k = tid; k < K; k += 256) chi2[k] = draws.tape_nw[k];
-        for (int q = tid; q < NB; q += 256) {
-            int r = (int)((1.0 + sqrt(1.0 + 8.0 * q)) * 0.5);
-            while (r * (r - 1) / 2 > q) --r;
-            while ((r + 1) * r / 2 <= q) ++r;
-            Tm[r * NCS + (q - r * (r - 1) / 2)] = draws.tape_nw[K + q];
-        }
-        for (int q = tid; q < K; q += 256) zm[q] = draws.tape_nw[K + NB + q];
-    } else {
-        const uint32_t h = half_sweep_index(draws);
-        for (int k = tid; k < K; k += 256)
-            chi2[k] = 2.0 * gamma_mt(draws.seed, h, (uint32_t)k, 0.5 * (nstar - (double)k));
-        // normal q of a stream is member q % 2 of Box-Muller pair q / 2
-        for (int p = tid; 2 * p < NB; p += 256) {
-            double z[2];
-            box_muller_f64(philox4x32_10(ctr4((uint32_t)p, 0u, h, 1u), draws.seed), z[0], z[1]);
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int q = 2 * p + u;
-                if (q < NB) {
-                    int r = (int)((1.0 + sqrt(1.0 + 8.0 * q)) * 0.5);
-                    while (r * (r - 1) / 2 > q) --r;
-                    while ((r + 1) * r / 2 <= q) ++r;
-                    Tm[r * NCS + (q - r * (r - 1) / 2)] = z[u];
-                }
-            }
-        }
-        for (int p = tid; 2 * p < K; p += 256) {
-            double z0, z1;
-            box_muller_f64(philox4x32_10(ctr4((uint32_t)p, 0u, h, 2u), draws.seed), z0, z1);
-            zm[2 * p] = z0;
-            if (2 * p + 1 < K) zm[2 * p + 1] = z1;
-        }
-    }
+    __syncthreads();
     // P = W0^{-1} + S + coef (xbar - mu0)(xbar - mu0)^T, identity padding
     {
         const double coef = beta0 * dn / bstar;
-        // unrolled by 4 so the loads of four entries are in flight together
-#pragma unroll 4
-        for (int e = tid; e < NWK * NWK; e += 256) {
-            const int i = e >> 6, j = e & 63;
+#pragma unroll
+        for (int u = 0; u < NWK * NWK / 256; ++u) {
+            const int e = tid + 256 * u, i = e >> 6, j = e & 63;
             double v = (i == j) ? 1.0 : 0.0;
             if (i < K && j < K) {
                 const int hi = i > j ? i : j, lo = i > j ? j : i;
                 const double S = sl[K + hi * (hi + 1) / 2 + lo] - dn * xbar[i] * xbar[j];
-                v = W0inv[i * K + j] + S + coef * (xbar[i] - mu0[i]) * (xbar[j] - mu0[j]);
+                v = w0r[u] + S + coef * (xbar[i] - mu0s[i]) * (xbar[j] - mu0s[j]);
             }
             Pm[i * NCS + j] = v;
         }
     }
     __syncthreads();
-    for (int m = tid; m < NWK; m += 256) Tm[m * NCS + m] = m < K ? sqrt(chi2[m]) : 1.0;
 
     // P = R R^T from the last pivot up, 8-column panels.  Wavefront 0 factors
     // a panel with lane i holding row i; then all four wavefronts update the
@@ -429,39 +434,76 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     }
     __syncthreads();
 
-    // Lambda = T T^T: thread (a, 16-column block of its wave); T[c][m] = 0 for m > c
+    // Lambda = T T^T on FP64 matrix cores: the ten lower 16 x 16 tiles (ta, tc)
+    // of the padded 64 x 64 product, tile (ta, tc) over k < 16 (tc + 1) (T is
+    // lower triangular), dealt to the wavefronts so each runs 20 rank-4 steps
+    // of v_mfma_f64_16x16x4_f64: wave 0 (3,3) (0,0); wave 1 (2,2) (1,1);
+    // wave 2 (3,2) (2,1); wave 3 (3,1) (1,0) (2,0) (3,0).  Operand lane l
+    // holds T[16 t + l % 16][4 kk + l / 16]; result element v of lane l is
+    // tile entry (4 v + l / 16, l % 16).  The padded T has the identity in the
+    // padding, so the product is Lambda with the identity padding.  Lambda
+    // also goes into Pm (free after the solve) for Lambda mu.
+    {
+        const int KPm = K <= 32 ? 32 : 64;  // padded size of the mixed row kernel
+        const int i16 = lane & 15, g = lane >> 4;
+        auto tile = [&](int ta, int tc) {
+            f64x4 c = {0.0, 0.0, 0.0, 0.0};
+            const double *ra = Tm + (16 * ta + i16) * NCS + g, *rc = Tm + (16 * tc + i16) * NCS + g;
+            for (int kk = 0; kk < 4 * (tc + 1); ++kk)
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[4 * kk], rc[4 * kk], c, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * ta + 4 * v + g, cc = 16 * tc + i16;
+                const double x = c[v];
+                Pm[r * NCS + cc] = x;
+                Pm[cc * NCS + r] = x;
+                if (r < K && cc < K) {
+                    hyp.Lambda[r * K + cc] = x;
+                    hyp.Lambda[cc * K + r] = x;
+                    hyp.Lambda_f[r * K + cc] = (float)x;
+                    hyp.Lambda_f[cc * K + r] = (float)x;
+                }
+                const int hi = r > cc ? r : cc, lo = r > cc ? cc : r;
+                if (hi < KPm) {
+                    hyp.Lambda_tri[hi * (hi + 1) / 2 + lo] = (float)x;
+                    if (hyp.Lambda_acc) {
+                        const int q0 = lambda_acc_index(r, cc), q1 = lambda_acc_index(cc, r);
+                        if (q0 >= 0) hyp.Lambda_acc[q0] = (float)x;
+                        if (q1 >= 0) hyp.Lambda_acc[q1] = (float)x;
+                    }
+                }
+            }
+        };
+        if (wave == 0) {
+            tile(3, 3);
+            tile(0, 0);
+        } else if (wave == 1) {
+            tile(2, 2);
+            tile(1, 1);
+        } else if (wave == 2) {
+            tile(3, 2);
+            tile(2, 1);
+        } else {
+            tile(3, 1);
+            tile(1, 0);
+            tile(2, 0);
+            tile(3, 0);
+        }
+        // T is chol(Lambda): lower with a positive diagonal, Lambda = T T^T
+        if (hyp.Lchol) {
+            for (int e = tid; e < KPm * KPm; e += 256) {
+                const int r = e / KPm, c = e % KPm;
+                hyp.Lchol[e] = (r < K && c < K) ? (c <= r ? (float)Tm[r * NCS + c] : 0.0f) : (r == c ? 1.0f : 0.0f);
+            }
+        }
+    }
+    __syncthreads();
+    // Lambda mu: thread (a, quarter w) sums columns 16 w .. 16 w + 15 of row a
     {
         const int a = lane, cb = 16 * wave;
-        double acc[16];
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) acc[cc] = 0.0;
-#pragma unroll 2
-        for (int m = 0; m < cb + 16; ++m) {
-            const double ta = Tm[a * NCS + m];
-#pragma unroll
-            for (int cc = 0; cc < 16; ++cc) acc[cc] = fma(ta, Tm[(cb + cc) * NCS + m], acc[cc]);
-        }
-        const int KPm = K <= 32 ? 32 : 64;  // padded size of the mixed row kernel
         double lmu = 0.0;
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) {
-            const int c = cb + cc;
-            if (a < K && c < K) {
-                hyp.Lambda[a * K + c] = acc[cc];
-                hyp.Lambda_f[a * K + c] = (float)acc[cc];
-            }
-            if (c <= a && a < KPm)
-                hyp.Lambda_tri[a * (a + 1) / 2 + c] = (a < K && c < K) ? (float)acc[cc] : (a == c ? 1.0f : 0.0f);
-            if (hyp.Lambda_acc && a < KPm && c < KPm) {
-                const int q = lambda_acc_index(a, c);
-                if (q >= 0) hyp.Lambda_acc[q] = (a < K && c < K) ? (float)acc[cc] : (a == c ? 1.0f : 0.0f);
-            }
-            // T is chol(Lambda): lower with a positive diagonal, Lambda = T T^T
-            if (hyp.Lchol && a < KPm && c < KPm)
-                hyp.Lchol[a * KPm + c] =
-                    (a < K && c < K) ? (c <= a ? (float)Tm[a * NCS + c] : 0.0f) : (a == c ? 1.0f : 0.0f);
-            lmu = fma(acc[cc], mul[c], lmu);
-        }
+        for (int cc = 0; cc < 16; ++cc) lmu = fma(Pm[a * NCS + cb + cc], mul[cb + cc], lmu);
         lpart[wave * NWK + a] = lmu;
     }
     if (hyp.Lchol && wave == 1) {
@@ -537,6 +579,8 @@ hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double bet
                      const double *W0inv, DevState *state, hipStream_t s)
 {
     if (K <= NWK) {
+        // the statistics launch always provides the draws as a tape here
+        if (!sides[0].draws.tape_nw || !sides[1].draws.tape_nw) return hipErrorInvalidValue;
         hipLaunchKernelGGL(nw_compact_kernel, dim3(2), dim3(256), nw_compact_lds_bytes(), s, sides[0], sides[1],
                            K, mu0, beta0, nu0, W0inv, state);
         return hipGetLastError();
