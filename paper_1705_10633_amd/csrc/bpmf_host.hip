@@ -126,8 +126,9 @@ static Offsets layout(const bpmf_ratings *R, const bpmf_params *p, int64_t n_tes
     const bool mixed = p->precision != BPMF_FP64;
     const bool mk = mixed && mixed_supported(K, p->precision);
     o.state = w.add(sizeof(DevState));
+    const int slots = stats_slots(K, p->precision == BPMF_FP64 ? 1 : 0);
     for (int s = 0; s < 2; ++s) {
-        const int nc = stats_chunks(n[s], K);
+        const int nc = stats_chunks(n[s], n[1 - s], K, slots);
         o.partials[s] = w.add(sizeof(double) * (size_t)nc * (K + K * (K + 1) / 2));
         o.sums[s] = w.add(sizeof(double) * (size_t)(K + K * (K + 1) / 2));
         o.lam[s] = w.add(sizeof(double) * K * K);
@@ -360,8 +361,9 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
     c->n_test = n_test;
     c->test_rows = d_test_rows;
     c->test_cols = d_test_cols;
+    const int slots = stats_slots(K, p->precision == BPMF_FP64 ? 1 : 0);
     for (int sd = 0; sd < 2; ++sd) {
-        c->n_chunks[sd] = stats_chunks(n[sd], K);
+        c->n_chunks[sd] = stats_chunks(n[sd], n[1 - sd], K, slots);
         c->hyp[sd].Lambda = c->at<double>(off.lam[sd]);
         c->hyp[sd].mu = c->at<double>(off.mu[sd]);
         c->hyp[sd].Lmu = c->at<double>(off.lmu[sd]);

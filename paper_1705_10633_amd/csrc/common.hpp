@@ -138,7 +138,8 @@ struct NwSide {
     HyperDev hyp;
 };
 hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s);
-int stats_chunks(int64_t n, int K);
+int stats_chunks(int64_t n, int64_t n_other, int K, int slots);
+int stats_slots(int K, int x_is_f64);
 hipError_t launch_stats_reduce(const StatsSides &ss, double *const sums[2], int K, hipStream_t s);
 hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double beta0, double nu0,
                      const double *W0inv, DevState *state, hipStream_t s);

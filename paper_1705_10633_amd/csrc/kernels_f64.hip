@@ -607,14 +607,49 @@ hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_
     return hipGetLastError();
 }
 
-// Row chunks of the side statistics: up to 256 of >= 512 rows for the
-// matrix-core kernel (K <= 64), whose per-chunk tree reduction and partial
-// write would otherwise dominate; up to 1024 of >= 128 rows above that, where
-// the per-row work is 4x larger and more blocks fill the device.
-int stats_chunks(int64_t n, int K)
+// Row chunks of the side statistics.  K <= 64 (matrix-core kernel, one
+// 512-thread block per chunk): the two sides share one round of the blocks
+// the device holds at once (`slots`, less the two blocks that draw the
+// Normal-Wishart randoms) in proportion to their rows, at least 64 rows a
+// chunk, so no compute unit runs a block after the others are done.  Above
+// K = 64: up to 1024 chunks of >= 128 rows, where the per-row work is 4x
+// larger and more blocks fill the device.
+int stats_chunks(int64_t n, int64_t n_other, int K, int slots)
 {
-    if (K <= 64) return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 511) / 512));
+    if (K <= 64) {
+        const int64_t budget = std::max(2, slots - 2);
+        const int64_t c = budget * n / std::max<int64_t>(1, n + n_other);
+        return (int)std::max<int64_t>(1, std::min<int64_t>(c, (n + 63) / 64));
+    }
     return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 127) / 128));
+}
+
+// Blocks of the K <= 64 statistics kernel the current device holds at once
+// (compute units x blocks per unit); 256 when the queries fail.
+int stats_slots(int K, int x_is_f64)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    if (K > 64) return cus;
+    const int NB = (K + 15) / 16;
+    const void *fn = nullptr;
+#define BPMF_STATS_FN(XT, N) fn = (const void *)stats_mfma_kernel<XT, N>
+    if (x_is_f64) {
+        if (NB == 1) BPMF_STATS_FN(double, 1);
+        else if (NB == 2) BPMF_STATS_FN(double, 2);
+        else if (NB == 3) BPMF_STATS_FN(double, 3);
+        else BPMF_STATS_FN(double, 4);
+    } else {
+        if (NB == 1) BPMF_STATS_FN(float, 1);
+        else if (NB == 2) BPMF_STATS_FN(float, 2);
+        else if (NB == 3) BPMF_STATS_FN(float, 3);
+        else BPMF_STATS_FN(float, 4);
+    }
+#undef BPMF_STATS_FN
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, STATS_THREADS, 0) != hipSuccess || per <= 0) per = 1;
+    return cus * per;
 }
 
 hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s)
