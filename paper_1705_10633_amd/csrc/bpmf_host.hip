@@ -571,8 +571,6 @@ static bpmf_status enqueue_hyper(bpmf_ctx *c, const DrawSrc &d0, const DrawSrc &
     }
     t0 = time_begin(c, s);
     HIP_OK(launch_nw(nw, K, c->at<double>(c->off.mu0), c->beta0, c->nu0, c->at<double>(c->off.w0inv), c->state, s));
-    if (K > 64 && !c->x_f64() && mixed_supported(K, c->precision))
-        for (int sd = 0; sd < 2; ++sd) HIP_OK(launch_lambda_tri(c->hyp[sd], K, c->KP, s));  // the K = 128 kernel's Lambda
     time_end(c, 1, t0, s);
     return BPMF_OK;
 }

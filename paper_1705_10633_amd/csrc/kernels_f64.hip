@@ -607,24 +607,19 @@ hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_
     return hipGetLastError();
 }
 
-// Row chunks of the side statistics.  K <= 64 (matrix-core kernel, one
-// 512-thread block per chunk): the two sides share one round of the blocks
-// the device holds at once (`slots`, less the two blocks that draw the
-// Normal-Wishart randoms) in proportion to their rows, at least 64 rows a
-// chunk, so no compute unit runs a block after the others are done.  Above
-// K = 64: up to 1024 chunks of >= 128 rows, where the per-row work is 4x
-// larger and more blocks fill the device.
+// Row chunks of the side statistics (one 512-thread block per chunk): the two
+// sides share one round of the blocks the device holds at once (`slots`, less
+// the two blocks that draw the Normal-Wishart randoms at K <= 64) in
+// proportion to their rows, at least 64 rows a chunk, so no compute unit runs
+// a block after the others are done.
 int stats_chunks(int64_t n, int64_t n_other, int K, int slots)
 {
-    if (K <= 64) {
-        const int64_t budget = std::max(2, slots - 2);
-        const int64_t c = budget * n / std::max<int64_t>(1, n + n_other);
-        return (int)std::max<int64_t>(1, std::min<int64_t>(c, (n + 63) / 64));
-    }
-    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 127) / 128));
+    const int64_t budget = std::max(2, slots - (K <= 64 ? 2 : 0));
+    const int64_t c = budget * n / std::max<int64_t>(1, n + n_other);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(c, (n + 63) / 64));
 }
 
-// Blocks of the K <= 64 statistics kernel the current device holds at once
+// Blocks of the statistics kernel for K the current device holds at once
 // (compute units x blocks per unit); 256 when the queries fail.
 int stats_slots(int K, int x_is_f64)
 {
@@ -632,11 +627,12 @@ int stats_slots(int K, int x_is_f64)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         return 256;
-    if (K > 64) return cus;
     const int NB = (K + 15) / 16;
     const void *fn = nullptr;
 #define BPMF_STATS_FN(XT, N) fn = (const void *)stats_mfma_kernel<XT, N>
-    if (x_is_f64) {
+    if (K > 64)
+        fn = x_is_f64 ? (const void *)stats_mfma_big_kernel<double> : (const void *)stats_mfma_big_kernel<float>;
+    else if (x_is_f64) {
         if (NB == 1) BPMF_STATS_FN(double, 1);
         else if (NB == 2) BPMF_STATS_FN(double, 2);
         else if (NB == 3) BPMF_STATS_FN(double, 3);

@@ -173,19 +173,26 @@ __global__ __launch_bounds__(NWP_THREADS) void nw_packed_kernel(NwSide side0, Nw
         for (int c = tid; c <= m; c += NWP_THREADS) TL[ptri(m, c)] *= irm;
         __syncthreads();
     }
-    // Lambda = T T^T (T(a, m) = 0 for m > a), entries (a, c) with a >= c and their mirror
-    for (int e = tid; e < KT; e += NWP_THREADS) {
-        int a = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-        while (ptri(a, 0) > e) --a;
-        while (ptri(a + 1, 0) <= e) ++a;
-        const int c = e - ptri(a, 0);
-        const double *ta = TL + ptri(a, 0), *tc = TL + ptri(c, 0);
-        double acc = 0.0;
-        for (int m = 0; m <= c; ++m) acc = fma(ta[m], tc[m], acc);
-        sd.hyp.Lambda[a * K + c] = acc;
-        sd.hyp.Lambda[c * K + a] = acc;
-        sd.hyp.Lambda_f[a * K + c] = (float)acc;
-        sd.hyp.Lambda_f[c * K + a] = (float)acc;
+    // Lambda = T T^T (T(a, m) = 0 for m > a), entries (a, c) with a >= c and
+    // their mirror, one row a per 16 threads; also the padded packed FP32
+    // triangle of the 128-wide row kernel (identity in the padding)
+    for (int a = tid >> 4; a < NWP_MAXK; a += NWP_THREADS / 16) {
+        const double *ta = TL + ptri(a < K ? a : 0, 0);
+        float *tri = sd.hyp.Lambda_tri + ptri(a, 0);
+        for (int c = tid & 15; c <= a; c += 16) {
+            if (a < K) {
+                const double *tc = TL + ptri(c, 0);
+                double acc = 0.0;
+                for (int m = 0; m <= c; ++m) acc = fma(ta[m], tc[m], acc);
+                sd.hyp.Lambda[a * K + c] = acc;
+                sd.hyp.Lambda[c * K + a] = acc;
+                sd.hyp.Lambda_f[a * K + c] = (float)acc;
+                sd.hyp.Lambda_f[c * K + a] = (float)acc;
+                tri[c] = (float)acc;
+            } else {
+                tri[c] = a == c ? 1.0f : 0.0f;
+            }
+        }
     }
     // mean: T^T d = z / sqrt(beta*), column-oriented backward substitution
     const double isb = 1.0 / sqrt(bstar);
