@@ -544,9 +544,9 @@ static bpmf_status enqueue_hyper(bpmf_ctx *c, const DrawSrc &d0, const DrawSrc &
     ss.X[1] = c->dV;
     ss.n[0] = c->R.M;
     ss.n[1] = c->R.N;
-    // with device draws and K <= 64 the statistics launch also draws the
-    // Normal-Wishart randoms, and the hyper step reads them like a tape
-    const bool pre = !d0.tape_nw && K <= 64;
+    // with device draws the statistics launch also draws the Normal-Wishart
+    // randoms (two extra blocks), and the hyper step reads them like a tape
+    const bool pre = !d0.tape_nw;
     ss.with_draws = pre ? 1 : 0;
     ss.nu0 = c->nu0;
     for (int sd = 0; sd < 2; ++sd) {

@@ -354,6 +354,12 @@ __device__ __forceinline__ void tile_ab(int t, int &a, int &b)
 template <typename XT>
 __global__ __launch_bounds__(STATS_THREADS) void stats_mfma_big_kernel(StatsSides ss, int K)
 {
+    const int nstat = ss.n_chunks[0] + ss.n_chunks[1];
+    if ((int)blockIdx.x >= nstat) {
+        const int sd = (int)blockIdx.x - nstat;
+        nw_draws_block(ss.draws[sd], K, ss.nu0 + (double)ss.n[sd], ss.draw_out[sd]);
+        return;
+    }
     __shared__ double stage[SB_ROWS][SB_NB * 16 + 1];
     const int side = (int)blockIdx.x >= ss.n_chunks[0] ? 1 : 0;
     const XT *X = (const XT *)ss.X[side];
@@ -609,12 +615,12 @@ hipError_t launch_mean_from_sum(const double *accum, const int64_t *perm, int64_
 
 // Row chunks of the side statistics (one 512-thread block per chunk): the two
 // sides share one round of the blocks the device holds at once (`slots`, less
-// the two blocks that draw the Normal-Wishart randoms at K <= 64) in
+// the two blocks that draw the Normal-Wishart randoms) in
 // proportion to their rows, at least 64 rows a chunk, so no compute unit runs
 // a block after the others are done.
 int stats_chunks(int64_t n, int64_t n_other, int K, int slots)
 {
-    const int64_t budget = std::max(2, slots - (K <= 64 ? 2 : 0));
+    const int64_t budget = std::max(2, slots - 2);
     const int64_t c = budget * n / std::max<int64_t>(1, n + n_other);
     return (int)std::max<int64_t>(1, std::min<int64_t>(c, (n + 63) / 64));
 }
@@ -671,7 +677,7 @@ hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s
         return hipGetLastError();
     }
     if (K <= SB_NB * 16) {
-        const unsigned grid = (unsigned)(ss.n_chunks[0] + ss.n_chunks[1]);
+        const unsigned grid = (unsigned)(ss.n_chunks[0] + ss.n_chunks[1] + (ss.with_draws ? 2 : 0));
         if (grid == 0) return hipSuccess;
         if (x_is_f64)
             hipLaunchKernelGGL((stats_mfma_big_kernel<double>), dim3(grid), dim3(STATS_THREADS), 0, s, ss, K);

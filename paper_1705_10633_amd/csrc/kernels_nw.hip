@@ -58,23 +58,39 @@ __global__ __launch_bounds__(256) void stats_reduce_kernel(StatsSides ss, double
 }
 
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 // 64 < K <= 128: both sides in one launch, one 512-thread workgroup per side,
 // every matrix in LDS as a packed lower triangle (row k at k (k + 1) / 2):
 //  * PL holds P (lower part), then row by row R^T: the factorisation from the
 //    last pivot computes column k of R, R_ik = P_ki / R_kk (i < k), into row
-//    k of PL in place and then removes R_k R_k^T from the leading block;
+//    k of PL in place.  It runs in panels of 8 columns: wavefront 0 factors a
+//    panel with rows l and l + 64 on lane l (pivots and in-panel values
+//    broadcast by readlane), copies the panel's columns into `pan`, and then
+//    all wavefronts remove the panel's rank-8 part from the leading block;
 //  * TL holds A (Bartlett factor, written straight from the draws) and then
-//    T, the solution of R^T T = A (R_mi with m < i is PL(i, m));
-//  * Lambda = T T^T goes to global memory, Lambda mu = T (T^T mu) and the mean
-//    solve T^T d = z / sqrt(beta*) read TL.
-// Two packed 128 x 128 triangles and the vectors take 139 KB of LDS.
+//    T, the solution of R^T T = A (R_mi with m < i is PL(i, m)), in blocks of
+//    8 rows: wavefront 0 solves a block with columns l and l + 64 on lane l,
+//    then all wavefronts remove the block from the rows below;
+//  * Lambda = T T^T (and the packed FP32 copy the 128-wide row kernel reads)
+//    goes to global memory; the mean solve T^T d = z / sqrt(beta*) runs on
+//    one wavefront; Lambda mu = T (T^T mu).
+// Every element of P sees the same sequence of multiply-adds as in an
+// unblocked right-looking factorisation.  Two packed 128 x 128 triangles, the
+// panel buffer and the vectors take 146 KB of LDS.
 // ---------------------------------------------------------------------------
 constexpr int NWP_THREADS = 512;
 constexpr int NWP_MAXK = 128;
+constexpr int NWP_W = 8;  // panel width
 
 __host__ __device__ constexpr size_t nw_packed_lds_doubles(int K)
 {
-    return (size_t)K * (K + 1) + 7 * (size_t)K;
+    return (size_t)K * (K + 1) + 7 * (size_t)K + (size_t)NWP_W * NWP_MAXK;
 }
 
 __device__ __forceinline__ int ptri(int r, int c) { return r * (r + 1) / 2 + c; }
@@ -87,90 +103,201 @@ __global__ __launch_bounds__(NWP_THREADS) void nw_packed_kernel(NwSide side0, Nw
     __shared__ int s_flag;
     const NwSide sd = blockIdx.x == 0 ? side0 : side1;
     const double *sums = sd.sums;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wavefront index in a scalar register: the branches on it are uniform
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int KT = K * (K + 1) / 2;
     double *PL = lds;             // P, then R^T (packed lower)
     double *TL = PL + KT;         // A, then T (packed lower)
     double *xbar = TL + KT;       // K
-    double *rd = xbar + K;        // K: diagonal of R
+    double *rd = xbar + K;        // K: 1 / diagonal of R
     double *chi2 = rd + K;        // K
     double *zm = chi2 + K;        // K
     double *dvec = zm + K;        // K
     double *dout = dvec + K;      // K
     double *tv = dout + K;        // K: T^T mu
+    double *pan = tv + K;         // NWP_W x 128: pan[q * 128 + i] = R_{i, c0 + q} of the current panel
     const double dn = (double)sd.n;
-    const double bstar = beta0 + dn, nstar = nu0 + dn;
+    const double bstar = beta0 + dn;
 
     if (tid == 0) s_flag = 0;
-    // draws: chi^2 and mean normals into vectors, Bartlett normals straight into TL
-    if (sd.draws.tape_nw) {
-        for (int k = tid; k < K; k += NWP_THREADS) chi2[k] = sd.draws.tape_nw[k];
-        for (int q = tid; q < K; q += NWP_THREADS) zm[q] = sd.draws.tape_nw[K + K * (K - 1) / 2 + q];
-    } else {
-        const uint32_t h = half_sweep_index(sd.draws);
-        for (int k = tid; k < K; k += NWP_THREADS)
-            chi2[k] = 2.0 * gamma_mt(sd.draws.seed, h, (uint32_t)k, 0.5 * (nstar - (double)k));
-        for (int q = tid; q < K; q += NWP_THREADS) zm[q] = stream_normal_f64(sd.draws.seed, h, 2u, (uint32_t)q);
-    }
+    // draws (always a tape: the statistics launch draws them when the sampler
+    // draws on the device): chi^2 and mean normals into vectors, Bartlett
+    // normals straight into TL
+    const double *tape = sd.draws.tape_nw;
+    for (int k = tid; k < K; k += NWP_THREADS) chi2[k] = tape[k];
+    for (int q = tid; q < K; q += NWP_THREADS) zm[q] = tape[K + K * (K - 1) / 2 + q];
     for (int a = tid; a < K; a += NWP_THREADS) xbar[a] = sd.n > 0 ? sums[a] / dn : 0.0;
     __syncthreads();
-    // A below the diagonal: Bartlett normal q = i (i - 1) / 2 + c for (i, c), c < i
-    for (int e = tid; e < KT; e += NWP_THREADS) {
-        int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-        while (ptri(i, 0) > e) --i;
-        while (ptri(i + 1, 0) <= e) ++i;
-        const int c = e - ptri(i, 0);
-        double v;
-        if (c == i) {
-            v = sqrt(chi2[c]);
-        } else {
-            const int q = i * (i - 1) / 2 + c;
-            v = sd.draws.tape_nw ? sd.draws.tape_nw[K + q] : stream_normal_f64(sd.draws.seed, half_sweep_index(sd.draws), 1u, (uint32_t)q);
-        }
-        TL[e] = v;
-        // P = W0^{-1} + S + coef (xbar - mu0)(xbar - mu0)^T, lower part
+    // A: the Bartlett normal q = i (i - 1) / 2 + c at (i, c), c < i, and
+    // sqrt(chi^2) on the diagonal; P = W0^{-1} + S + coef (xbar - mu0)(xbar - mu0)^T,
+    // lower part; one row per 16 threads
+    {
         const double coef = beta0 * dn / bstar;
-        const double S = sums[K + e] - dn * xbar[i] * xbar[c];
-        PL[e] = W0inv[i * K + c] + S + coef * (xbar[i] - mu0[i]) * (xbar[c] - mu0[c]);
-    }
-    // P = R R^T from the last pivot up
-    for (int k = K - 1; k >= 0; --k) {
-        __syncthreads();
-        double akk = PL[ptri(k, k)];
-        if (!(akk > 0.0) || !isfinite(akk)) {
-            if (tid == 0) s_flag = 1;
-            akk = 1.0;
-        }
-        const double rkk = sqrt(akk), inv = 1.0 / rkk;
-        __syncthreads();
-        if (tid == 0) {
-            rd[k] = rkk;
-            PL[ptri(k, k)] = rkk;
-        }
-        for (int i = tid; i < k; i += NWP_THREADS) PL[ptri(k, i)] *= inv;
-        __syncthreads();
-        // leading block: PL(ii, jj) -= R_ii,k R_jj,k for jj <= ii < k; 32
-        // rows at a time, 16 threads along a row
-        const double *rk = PL + ptri(k, 0);
-        for (int ii = tid >> 4; ii < k; ii += NWP_THREADS / 16) {
-            const double r = rk[ii];
-            double *row = PL + ptri(ii, 0);
-            for (int jj = tid & 15; jj <= ii; jj += 16) row[jj] = fma(-r, rk[jj], row[jj]);
+        for (int i = tid >> 4; i < K; i += NWP_THREADS / 16) {
+            for (int c = tid & 15; c <= i; c += 16) {
+                const int e = ptri(i, c), q = i * (i - 1) / 2 + c;
+                const double v = tape[c == i ? 0 : K + q];
+                TL[e] = c == i ? sqrt(chi2[c]) : v;
+                const double S = sums[K + e] - dn * xbar[i] * xbar[c];
+                PL[e] = W0inv[i * K + c] + S + coef * (xbar[i] - mu0[i]) * (xbar[c] - mu0[c]);
+            }
         }
     }
     __syncthreads();
-    // R^T T = A, right-looking: step m fixes row m of T and removes it from
-    // the rows below (TL(i, c) -= R_mi T_mc for i > m, c <= m)
-    for (int m = 0; m < K; ++m) {
-        const double irm = 1.0 / rd[m];
-        const double *tm = TL + ptri(m, 0);
-        for (int i = m + 1 + (tid >> 4); i < K; i += NWP_THREADS / 16) {
-            const double rmi = PL[ptri(i, m)] * irm;
-            double *ti = TL + ptri(i, 0);
-            for (int c = tid & 15; c <= m; c += 16) ti[c] = fma(-rmi, tm[c], ti[c]);
+
+    // P = R R^T from the last pivot up, 8-column panels [c0, c1)
+    for (int c1 = K; c1 > 0; c1 -= NWP_W) {
+        const int c0 = c1 > NWP_W ? c1 - NWP_W : 0, w = c1 - c0;
+        if (wave == 0) {
+            // a[s][q] = PL(c0 + q, i) for row i = lane + 64 s; entries with
+            // i > c0 + q do not exist and are never stored
+            double a[2][NWP_W];
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                for (int q = 0; q < NWP_W; ++q) {
+                    const int i = lane + 64 * s2, k = c0 + q;
+                    a[s2][q] = (q < w && i <= k) ? PL[ptri(k, i)] : 0.0;
+                }
+#pragma unroll
+            for (int q = NWP_W - 1; q >= 0; --q) {
+                if (q >= w) continue;
+                const int k = c0 + q;
+                double akk = readlane_d((k >> 6) ? a[1][q] : a[0][q], k & 63);
+                if (!(akk > 0.0) || !isfinite(akk)) {
+                    if (lane == 0) s_flag = 1;
+                    akk = 1.0;
+                }
+                // 1/sqrt(akk): hardware estimate refined by three Newton steps
+                double inv = __builtin_amdgcn_rsq(akk);
+                inv = inv * fma(-0.5 * akk * inv, inv, 1.5);
+                inv = inv * fma(-0.5 * akk * inv, inv, 1.5);
+                inv = inv * fma(-0.5 * akk * inv, inv, 1.5);
+                const double rkk = akk * inv;
+                if (lane == 0) rd[k] = inv;
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const int i = lane + 64 * s2;
+                    a[s2][q] = i < k ? a[s2][q] * inv : (i == k ? rkk : a[s2][q]);
+                }
+                // the panel's earlier columns: PL(k2, i) -= R_ik R_{k2,k}, c0 <= k2 < k
+#pragma unroll
+                for (int q2 = 0; q2 < NWP_W; ++q2) {
+                    if (q2 >= q) continue;
+                    const int k2 = c0 + q2;
+                    const double rk2 = readlane_d((k2 >> 6) ? a[1][q] : a[0][q], k2 & 63);
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2) a[s2][q2] = fma(-a[s2][q], rk2, a[s2][q2]);
+                }
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                for (int q = 0; q < NWP_W; ++q) {
+                    const int i = lane + 64 * s2, k = c0 + q;
+                    if (q < w && i <= k) PL[ptri(k, i)] = a[s2][q];
+                    if (q < w && i < c0) pan[q * NWP_MAXK + i] = a[s2][q];
+                }
         }
         __syncthreads();
-        for (int c = tid; c <= m; c += NWP_THREADS) TL[ptri(m, c)] *= irm;
+        if (c0 == 0) break;
+        // leading block: PL(i, j) -= R_ik R_jk over the panel, last column
+        // first, for j <= i < c0; one row per 16 threads
+        for (int i = tid >> 4; i < c0; i += NWP_THREADS / 16) {
+            double ri[NWP_W];
+#pragma unroll
+            for (int q = 0; q < NWP_W; ++q) ri[q] = q < w ? pan[q * NWP_MAXK + i] : 0.0;
+            double *row = PL + ptri(i, 0);
+            // four entries of the row at a time: their loads are issued together
+            for (int j0 = tid & 15; j0 <= i; j0 += 64) {
+                double t[4], pv[4][NWP_W];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + 16 * u, jc = j <= i ? j : i;
+                    t[u] = row[jc];
+#pragma unroll
+                    for (int q = 0; q < NWP_W; ++q) pv[u][q] = pan[q * NWP_MAXK + jc];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int q = NWP_W - 1; q >= 0; --q)
+                        if (q < w) t[u] = fma(-ri[q], pv[u][q], t[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j0 + 16 * u <= i) row[j0 + 16 * u] = t[u];
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // R^T T = A in blocks of 8 rows [i0, i1): T_i = (A_i - sum_{m < i} R_mi T_m) / R_ii
+    for (int i0 = 0; i0 < K; i0 += NWP_W) {
+        const int i1 = i0 + NWP_W < K ? i0 + NWP_W : K, w = i1 - i0;
+        if (wave == 0) {
+            // t[s][q] = TL(i0 + q, c) for column c = lane + 64 s (c <= i0 + q)
+            double t[2][NWP_W];
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                for (int q = 0; q < NWP_W; ++q) {
+                    const int c = lane + 64 * s2, i = i0 + q;
+                    t[s2][q] = (q < w && c <= i) ? TL[ptri(i, c)] : 0.0;
+                }
+#pragma unroll
+            for (int q = 0; q < NWP_W; ++q) {
+                if (q >= w) continue;
+                const double irm = rd[i0 + q];
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) t[s2][q] *= irm;
+#pragma unroll
+                for (int q2 = 0; q2 < NWP_W; ++q2) {
+                    if (q2 <= q || q2 >= w) continue;
+                    const double r = PL[ptri(i0 + q2, i0 + q)];  // R_{i0+q, i0+q2}
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2) t[s2][q2] = fma(-r, t[s2][q], t[s2][q2]);
+                }
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+                for (int q = 0; q < NWP_W; ++q) {
+                    const int c = lane + 64 * s2, i = i0 + q;
+                    if (q < w && c <= i) TL[ptri(i, c)] = t[s2][q];
+                }
+        }
+        __syncthreads();
+        if (i1 == K) break;
+        // rows below: TL(i, c) -= R_{i0+q, i} T_{i0+q, c} over the block, for
+        // i >= i1 and c < i1 (T_{i0+q, c} = 0 for c > i0 + q); one row per 16 threads
+        for (int i = i1 + (tid >> 4); i < K; i += NWP_THREADS / 16) {
+            double rr[NWP_W];
+#pragma unroll
+            for (int q = 0; q < NWP_W; ++q) rr[q] = q < w ? PL[ptri(i, i0 + q)] : 0.0;
+            double *ti = TL + ptri(i, 0);
+            // four entries of the row at a time: their loads are issued together
+            for (int cb = tid & 15; cb < i1; cb += 64) {
+                double u[4], tv2[4][NWP_W];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = cb + 16 * v, cc = c < i1 ? c : i1 - 1;
+                    u[v] = ti[cc];
+#pragma unroll
+                    for (int q = 0; q < NWP_W; ++q) tv2[v][q] = TL[ptri(i0 + q, cc <= i0 + q ? cc : i0 + q)];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = cb + 16 * v;
+#pragma unroll
+                    for (int q = 0; q < NWP_W; ++q)
+                        if (q < w && c <= i0 + q) u[v] = fma(-rr[q], tv2[v][q], u[v]);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (cb + 16 * v < i1) ti[cb + 16 * v] = u[v];
+            }
+        }
         __syncthreads();
     }
     // Lambda = T T^T (T(a, m) = 0 for m > a), entries (a, c) with a >= c and
@@ -194,15 +321,18 @@ __global__ __launch_bounds__(NWP_THREADS) void nw_packed_kernel(NwSide side0, Nw
             }
         }
     }
-    // mean: T^T d = z / sqrt(beta*), column-oriented backward substitution
-    const double isb = 1.0 / sqrt(bstar);
-    for (int a = tid; a < K; a += NWP_THREADS) dvec[a] = zm[a] * isb;
-    for (int k = K - 1; k >= 0; --k) {
-        __syncthreads();
-        const double dk = dvec[k] / TL[ptri(k, k)];
-        __syncthreads();
-        if (tid == 0) dout[k] = dk;
-        for (int i = tid; i < k; i += NWP_THREADS) dvec[i] = fma(-TL[ptri(k, i)], dk, dvec[i]);
+    // mean: T^T d = z / sqrt(beta*), column-oriented backward substitution on
+    // wavefront 0 with entries l and l + 64 on lane l
+    if (wave == 0) {
+        const double isb = 1.0 / sqrt(bstar);
+        double r0 = lane < K ? zm[lane] * isb : 0.0, r1 = lane + 64 < K ? zm[lane + 64] * isb : 0.0;
+        for (int k = K - 1; k >= 0; --k) {
+            const double dk = readlane_d(k >= 64 ? r1 : r0, k & 63) / TL[ptri(k, k)];
+            if (lane == 0) dout[k] = dk;
+            const double t0 = TL[ptri(k, lane < k ? lane : k)], t1 = TL[ptri(k, lane + 64 < k ? lane + 64 : k)];
+            if (lane < k) r0 = fma(-t0, dk, r0);
+            if (lane + 64 < k) r1 = fma(-t1, dk, r1);
+        }
     }
     __syncthreads();
     for (int a = tid; a < K; a += NWP_THREADS) {
@@ -229,13 +359,6 @@ __global__ __launch_bounds__(NWP_THREADS) void nw_packed_kernel(NwSide side0, Nw
 
 constexpr int NWK = 64;       // padded size (K <= 64)
 constexpr int NPW = 8;        // panel width
-
-__device__ __forceinline__ double readlane_d(double v, int l)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
 
 // ---------------------------------------------------------------------------
 // K <= 64, compact form: P, R and T live in LDS (padded to 64, identity in
@@ -585,9 +708,9 @@ hipError_t launch_stats_reduce(const StatsSides &ss, double *const sums[2], int 
 hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double beta0, double nu0,
                      const double *W0inv, DevState *state, hipStream_t s)
 {
+    // the statistics launch always provides the draws as a tape here
+    if (!sides[0].draws.tape_nw || !sides[1].draws.tape_nw) return hipErrorInvalidValue;
     if (K <= NWK) {
-        // the statistics launch always provides the draws as a tape here
-        if (!sides[0].draws.tape_nw || !sides[1].draws.tape_nw) return hipErrorInvalidValue;
         hipLaunchKernelGGL(nw_compact_kernel, dim3(2), dim3(256), nw_compact_lds_bytes(), s, sides[0], sides[1],
                            K, mu0, beta0, nu0, W0inv, state);
         return hipGetLastError();
