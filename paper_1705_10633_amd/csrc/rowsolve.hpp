@@ -582,10 +582,47 @@ __device__ __forceinline__ float backward_sub(const float *tri, float invd, floa
     return xbuf[ri];
 }
 
+// The two solves with every row of L divided by its own diagonal entry
+// (L' = D^-1 L, unit diagonal, D = diag(L)):
+//  * L y = b  is  L' y = D^-1 b;
+//  * L^T x = w  is  L'^T u = w  with  u = D x  (L_ik x_i = L'_ik u_i), so
+//    x = D^-1 u.
+// Both are unit-diagonal solves: each step of their serial chains is one
+// broadcast and one multiply-add.  A holds row ri of L' (registers); `tri` its
+// packed rows.  ybuf and xbuf hold KP floats.
+template <int KP, class Sync = BlockSync>
+__device__ __forceinline__ float forward_sub_unit(const float (&A)[KP], float bb, float *ybuf)
+{
+    const int ri = (threadIdx.x & 63) % KP;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const float yk = readlane_f(bb, k);
+        ybuf[k] = yk;
+        bb = fmaf(-A[k], yk, bb);
+    }
+    Sync::sync();
+    return ybuf[ri];
+}
+
+template <int KP, class Sync = BlockSync>
+__device__ __forceinline__ float backward_sub_unit(const float *tri, float w, float *xbuf)
+{
+    const int ri = (threadIdx.x & 63) % KP;
+#pragma unroll
+    for (int k = KP - 1; k >= 0; --k) {
+        const float uk = readlane_f(w, k);
+        xbuf[k] = uk;
+        w = fmaf(-tri[k * (k + 1) / 2 + ri], uk, w);
+    }
+    Sync::sync();
+    return xbuf[ri];
+}
+
 // Factor P (packed in `tri`) and return x = L^{-T}(L^{-1} b + z) on lane
 // ri = lane % KP, where lane ri holds b_ri and z_ri.  `fail` is set (uniformly
 // across the wave) when a pivot is not finite or not above
-// 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with L; `aux` holds 3 KP floats.
+// 64 K 2^-24 max_{k<K} P_kk.  Overwrites `tri` with D^-1 L (rows of L divided
+// by their diagonal entries); `aux` holds 3 KP floats.
 // Lane ri keeps row ri of P in registers through chol_factor.
 template <int KP, class Sync = BlockSync, bool MT = true>
 __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float bb, float z,
@@ -606,10 +643,13 @@ __device__ __forceinline__ float chol_solve(float *tri, float *aux, int K, float
     chol_factor<KP, Sync, MT>(A, invbuf, tri);  // P is in registers: tri serves as the panel buffer
     fail = chol_pivots_fail(invbuf[ri], ri, K, tau);
     const float invd = invbuf[ri];
-    const float y = forward_sub<KP, Sync>(A, invd, bb, ybuf);
+    // rows of L' = D^-1 L for the unit-diagonal solves
+#pragma unroll
+    for (int c = 0; c < KP; ++c) A[c] *= invd;
+    const float y = forward_sub_unit<KP, Sync>(A, bb * invd, ybuf);
     store_rows<KP>(A, tri);
     Sync::sync();
-    const float x = backward_sub<KP, Sync>(tri, invd, y + z, xbuf);
+    const float x = backward_sub_unit<KP, Sync>(tri, y + z, xbuf) * invd;
     Sync::sync();
     return x;
 }
