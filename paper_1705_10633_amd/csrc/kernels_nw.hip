@@ -399,6 +399,9 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NB = K * (K - 1) / 2;
     const double dn = (double)n, bstar = beta0 + dn;
+    // the three sequential parts and Lambda stop at NP = 32 when K <= 32: the
+    // padding beyond is the identity, which they would leave unchanged
+    const int NP = K <= 32 ? 32 : NWK;
 
     // Every global read of the side is issued first, together: the sums, the
     // prior's W0^{-1} (16 entries per thread, kept in registers), mu0 and the
@@ -466,7 +469,7 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     // P = R R^T from the last pivot up, 8-column panels.  Wavefront 0 factors
     // a panel with lane i holding row i; then all four wavefronts update the
     // leading block (columns j < c0 split over the wavefronts).
-    for (int c0 = NWK - NPW; c0 >= 0; c0 -= NPW) {
+    for (int c0 = NP - NPW; c0 >= 0; c0 -= NPW) {
         if (wave == 0) {
             double a[NPW];
 #pragma unroll
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     // R^T T = A, forward over 8-row blocks with lane m holding column m:
     // wavefront 0 solves a block's diagonal part, then all four wavefronts
     // update the rows below (split over the wavefronts)
-    for (int i0 = 0; i0 < NWK; i0 += NPW) {
+    for (int i0 = 0; i0 < NP; i0 += NPW) {
         if (wave == 0) {
             double t[NPW];
 #pragma unroll
@@ -528,14 +531,14 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
 #pragma unroll
             for (int q = 0; q < NPW; ++q) Tm[(i0 + q) * NCS + lane] = t[q];
         }
-        if (i0 + NPW == NWK) break;
+        if (i0 + NPW == NP) break;
         __syncthreads();
         {
             double t[NPW];
 #pragma unroll
             for (int q = 0; q < NPW; ++q) t[q] = Tm[(i0 + q) * NCS + lane];
 #pragma unroll 2
-            for (int i = i0 + NPW + wave; i < NWK; i += 4) {
+            for (int i = i0 + NPW + wave; i < NP; i += 4) {
                 double u = Tm[i * NCS + lane];
 #pragma unroll
                 for (int q = 0; q < NPW; ++q) u = fma(-Pm[(i0 + q) * NCS + i], t[q], u);
@@ -549,7 +552,7 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
         // mean: T^T d = z / sqrt(beta*), backward; lane i holds right-hand side i
         const double it = 1.0 / Tm[lane * NCS + lane];
         double rhs = lane < K ? zm[lane] * (1.0 / sqrt(bstar)) : 0.0;
-        for (int k = NWK - 1; k >= 0; --k) {
+        for (int k = NP - 1; k >= 0; --k) {
             const double dk = readlane_d(rhs * it, k);
             if (lane == 0) dvec[k] = dk;
             rhs = fma(-Tm[k * NCS + lane], dk, rhs);
@@ -577,6 +580,7 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
         const int KPm = K <= 32 ? 32 : 64;  // padded size of the mixed row kernel
         const int i16 = lane & 15, g = lane >> 4;
         auto tile = [&](int ta, int tc) {
+            if (16 * ta >= NP) return;
             f64x4 c = {0.0, 0.0, 0.0, 0.0};
             const double *ra = Tm + (16 * ta + i16) * NCS + g, *rc = Tm + (16 * tc + i16) * NCS + g;
             for (int kk = 0; kk < 4 * (tc + 1); ++kk)
@@ -632,8 +636,10 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     {
         const int a = lane, cb = 16 * wave;
         double lmu = 0.0;
+        if (cb < NP) {
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) lmu = fma(Pm[a * NCS + cb + cc], mul[cb + cc], lmu);
+            for (int cc = 0; cc < 16; ++cc) lmu = fma(Pm[a * NCS + cb + cc], mul[cb + cc], lmu);
+        }
         lpart[wave * NWK + a] = lmu;
     }
     if (hyp.Lchol && wave == 1) {
