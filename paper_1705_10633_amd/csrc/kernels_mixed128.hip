@@ -197,14 +197,27 @@ __global__ __launch_bounds__(T2) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         if (t < ntile) {
             int ta, tb;
             tile_of(wave, t, ta, tb);
+            // the tile's 16 entries of Lambda are requested together, before
+            // any of them is used: interleaved with the stores, each load
+            // was issued only after the previous one had returned
+            float lam[16];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = 32 * ta + 8 * j + 4 * (lane >> 5) + i;
                     const int c = 32 * tb + (lane & 31);
-                    const int e = rowoff(r) + c;  // < PTRI2 + K2 for every lane
-                    const float val = fmaf(alpha, acc[t][4 * j + i], hyp.Lambda_tri[e]);
+                    lam[4 * j + i] = hyp.Lambda_tri[rowoff(r) + c];  // < PTRI2 + K2 for every lane
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 32 * ta + 8 * j + 4 * (lane >> 5) + i;
+                    const int c = 32 * tb + (lane & 31);
+                    const int e = rowoff(r) + c;
+                    const float val = fmaf(alpha, acc[t][4 * j + i], lam[4 * j + i]);
                     // above the diagonal: a slot in the padding after the
                     // triangle, so the store (and the load) stay unconditional
                     P[c <= r ? e : PTRI2 + lane] = val;

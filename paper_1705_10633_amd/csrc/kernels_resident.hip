@@ -56,25 +56,31 @@ __device__ __attribute__((noinline)) void sample_mean(int w, int K, int64_t N, f
     float *colbuf = rv + 64;
     int *sidx = (int *)(colbuf + 3 * KP);
     const int lane = threadIdx.x & 63;
-    const float *V = Vs + (int64_t)w * N * K;
-    const double *L = Lam + (int64_t)w * K * K;
+    // the arguments point to global memory; as plain pointers into a
+    // function that is not inlined their loads would be flat loads, each
+    // ordered against the wavefront's LDS accesses
+    using gfloat = const __attribute__((address_space(1))) float;
+    using gint = const __attribute__((address_space(1))) int32_t;
+    using gdouble = const __attribute__((address_space(1))) double;
+    gfloat *V = (gfloat *)(Vs + (int64_t)w * N * K);
+    gdouble *L = (gdouble *)(Lam + (int64_t)w * K * K);
     floatx16 acc[SH::NTILE];
 #pragma unroll
     for (int t = 0; t < SH::NTILE; ++t)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
     float bacc = 0.0f;
-    gram_f32<KP, WaveSync>(dcols, dvals, nnz, V, K, rbar, u, rv, sidx, acc, bacc);
+    gram_f32<KP, WaveSync>((gint *)dcols, (gfloat *)dvals, nnz, V, K, rbar, u, rv, sidx, acc, bacc);
     store_precision<KP>(u, acc, K, alpha, [=](int rr, int cc) { return (float)L[rr * K + cc]; });
     const int ri = lane % KP;
-    const float bb = ri < K ? fmaf(alpha, bacc, lam_mu[(int64_t)w * K + ri]) : 0.0f;
+    const float bb = ri < K ? fmaf(alpha, bacc, ((gfloat *)lam_mu)[(int64_t)w * K + ri]) : 0.0f;
     WaveSync::sync();
     bool fail;
     const float m = chol_solve<KP, WaveSync>(u, colbuf, K, bb, 0.0f, fail);
     if (lane < KP) colbuf[lane] = (ri < K) ? (fail ? __builtin_nanf("") : m) : 0.0f;
     WaveSync::sync();
     for (int q = lane; q < nq; q += 64) {
-        const float *v = V + (int64_t)dq[q] * K;
+        gfloat *v = V + (int64_t)((gint *)dq)[q] * K;
         float p = 0.0f;
         for (int i = 0; i < K; ++i) p = fmaf(colbuf[i], v[i], p);
         u[q] = p;

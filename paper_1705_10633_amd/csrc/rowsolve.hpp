@@ -205,9 +205,13 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
 }
 
 // FP32 gathers of rows `idx` of `src` (row stride K), Gram on FP32 matrix cores.
-template <int KP, class Sync = BlockSync>
-__device__ __forceinline__ void gram_f32(const int32_t *idx, const float *vals, int64_t nnz,
-                                         const float *src, int K, float rbar, float *stage,
+// IP and FP are the index and value pointer types: plain pointers, or
+// pointers into the global address space where the caller cannot otherwise
+// tell the compiler so (its loads would be flat loads, ordered against the
+// LDS accesses).
+template <int KP, class Sync = BlockSync, typename IP = const int32_t *, typename FP = const float *>
+__device__ __forceinline__ void gram_f32(IP idx, FP vals, int64_t nnz,
+                                         FP src, int K, float rbar, float *stage,
                                          float *rv, int *sidx, floatx16 *acc, float &bacc)
 {
     using S = RowShape<KP>;
@@ -260,20 +264,38 @@ __device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc,
 {
     using S = RowShape<KP>;
     const int lane = threadIdx.x & 63;
+    // entries above the diagonal go to the lane's own slot in the padding
+    // after the triangle, so no store (and no load feeding it) sits behind a
+    // branch of its own
+    const int dump = KP * (KP + 1) / 2 + lane % KP;
 #pragma unroll
     for (int t = 0; t < S::NTILE; ++t) {
         const int ta = (t == 0) ? 0 : 1, tb = (t == 2) ? 1 : 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int h = 0; h < 2; ++h) {
+            // half a tile's entries of Lambda are requested before any is used
+            float lv[8];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = 32 * ta + 8 * j + 4 * (lane >> 5) + i;
-                const int c = 32 * tb + (lane & 31);
-                const bool in = r < K && c < K;
-                const float l = lam(in ? r : 0, in ? c : 0);
-                const float v = in ? fmaf(alpha, acc[t][4 * j + i], l) : ((r == c) ? 1.0f : 0.0f);
-                if (c <= r) tri[r * (r + 1) / 2 + c] = v;
-            }
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 32 * ta + 8 * (2 * h + j) + 4 * (lane >> 5) + i;
+                    const int c = 32 * tb + (lane & 31);
+                    const bool in = r < K && c < K;
+                    lv[4 * j + i] = lam(in ? r : 0, in ? c : 0);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 32 * ta + 8 * (2 * h + j) + 4 * (lane >> 5) + i;
+                    const int c = 32 * tb + (lane & 31);
+                    const bool in = r < K && c < K;
+                    const float v = in ? fmaf(alpha, acc[t][4 * (2 * h + j) + i], lv[4 * j + i]) : ((r == c) ? 1.0f : 0.0f);
+                    tri[c <= r ? r * (r + 1) / 2 + c : dump] = v;
+                }
+        }
     }
 }
 
