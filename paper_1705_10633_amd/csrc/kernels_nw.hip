@@ -378,6 +378,10 @@ size_t nw_compact_lds_bytes()
     return sizeof(double) * ((size_t)2 * NWK * NCS + 11 * NWK + NSUMS);
 }
 
+// NP: the padded size the three sequential parts and Lambda run to (32 when
+// K <= 32, else 64); the padding beyond is the identity, which they would
+// leave unchanged.  A template parameter, so every loop bound is a constant.
+template <int NP>
 __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide side1, int K,
                                                          const double *mu0, double beta0, double nu0,
                                                          const double *W0inv, DevState *state)
@@ -399,9 +403,6 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NB = K * (K - 1) / 2;
     const double dn = (double)n, bstar = beta0 + dn;
-    // the three sequential parts and Lambda stop at NP = 32 when K <= 32: the
-    // padding beyond is the identity, which they would leave unchanged
-    const int NP = K <= 32 ? 32 : NWK;
 
     // Every global read of the side is issued first, together: the sums, the
     // prior's W0^{-1} (16 entries per thread, kept in registers), mu0 and the
@@ -686,8 +687,11 @@ __global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, in
 
 hipError_t prepare_nw()
 {
-    hipError_t e = hipFuncSetAttribute((const void *)nw_compact_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)nw_compact_lds_bytes());
+    hipError_t e = hipFuncSetAttribute((const void *)nw_compact_kernel<32>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)nw_compact_lds_bytes());
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)nw_compact_kernel<NWK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)nw_compact_lds_bytes());
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)nw_packed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(sizeof(double) * nw_packed_lds_doubles(NWP_MAXK)));
@@ -717,8 +721,12 @@ hipError_t launch_nw(const NwSide sides[2], int K, const double *mu0, double bet
     // the statistics launch always provides the draws as a tape here
     if (!sides[0].draws.tape_nw || !sides[1].draws.tape_nw) return hipErrorInvalidValue;
     if (K <= NWK) {
-        hipLaunchKernelGGL(nw_compact_kernel, dim3(2), dim3(256), nw_compact_lds_bytes(), s, sides[0], sides[1],
-                           K, mu0, beta0, nu0, W0inv, state);
+        if (K <= 32)
+            hipLaunchKernelGGL(nw_compact_kernel<32>, dim3(2), dim3(256), nw_compact_lds_bytes(), s, sides[0],
+                               sides[1], K, mu0, beta0, nu0, W0inv, state);
+        else
+            hipLaunchKernelGGL(nw_compact_kernel<NWK>, dim3(2), dim3(256), nw_compact_lds_bytes(), s, sides[0],
+                               sides[1], K, mu0, beta0, nu0, W0inv, state);
         return hipGetLastError();
     }
     if (K <= NWP_MAXK) {
