@@ -370,6 +370,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         c->hyp[sd].Lambda_f = c->at<float>(off.lamf[sd]);
         c->hyp[sd].Lmu_f = c->at<float>(off.lmuf[sd]);
         c->hyp[sd].Lambda_tri = c->at<float>(off.lamt[sd]);
+        c->hyp[sd].alpha = p->alpha;
         c->hyp[sd].Lambda_acc = (mixed_supported(K, p->precision) && p->precision != BPMF_FP64 && K <= 64)
                                     ? c->at<float>(off.lamacc[sd]) : nullptr;
         c->hyp[sd].Lchol = (mixed_supported(K, p->precision) && p->precision != BPMF_FP64 && K <= 64)

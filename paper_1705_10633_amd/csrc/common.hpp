@@ -46,11 +46,13 @@ struct HyperDev {
     // FP32 Lambda as the mixed row kernel's packed lower triangle of the
     // padded size KP (row r at r (r + 1) / 2, identity in the padding), KP (KP + 3) / 2 floats
     float *Lambda_tri;
-    // FP32 Lambda in the K <= 64 row kernel's Gram accumulator layout, or
-    // NULL: entry (t * 16 + e) * 64 + l is Lambda[r][c] of lower 32 x 32
-    // tile t ((0,0), (1,0), (1,1)), r = 32 a + 8 (e / 4) + 4 (l / 32) + e % 4,
-    // c = 32 b + l % 32 (identity in the padding)
+    // FP32 Lambda / alpha in the K <= 64 row kernel's Gram accumulator
+    // layout, or NULL: entry (t * 16 + e) * 64 + l is Lambda[r][c] / alpha of
+    // lower 32 x 32 tile t ((0,0), (1,0), (1,1)), r = 32 a + 8 (e / 4) +
+    // 4 (l / 32) + e % 4, c = 32 b + l % 32 (identity in the padding); the
+    // row kernel's accumulators start from it
     float *Lambda_acc;
+    double alpha;    // the sampler's alpha
     // chol(Lambda) in FP32 for the rank-one row paths (K <= 64), or NULL:
     // KP x KP row-major (lower; identity in the padding), then KP floats each
     // of 1 / L_ii, L^T mu (= L^{-1} Lambda mu), Lambda_ii (0 in the padding)

@@ -34,7 +34,7 @@ namespace {
 // wavefronts per SIMD the register allocation is held to (W = 4: at most 128
 // VGPRs; W = 3: 168).
 template <int KP, bool BF16, bool MT = true, int W = 4>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void rows_mixed_kernel(SideArgs a, int K, float alpha, float rbar,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void rows_mixed_kernel(SideArgs a, int K, float ialpha, float rsalpha, float rbar,
                                                         HyperDev hyp, DrawSrc draws,
                                                         int32_t *fb_list, DevState *state,
                                                         int side, PieceArgs pc)
@@ -49,7 +49,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
     const int lane = threadIdx.x;
     const float *vals = (const float *)a.val;
 
-    // gram_bf16 starts the accumulators itself; the other paths clear them
+    // The row is sampled from P / alpha = Lambda / alpha + G, whose factor is
+    // chol(P) / sqrt(alpha): with b / alpha and z / sqrt(alpha) in place of b
+    // and z the solves give the same x.  A row's Gram accumulators start from
+    // Lambda / alpha (in their own layout); a piece's, and a combined heavy
+    // row's, from zero.
     floatx16 acc[S::NTILE];
     float bacc = 0.0f;
     auto clear_acc = [&]() {
@@ -57,6 +61,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
         for (int t = 0; t < S::NTILE; ++t)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
+    };
+    auto lambda_acc = [&]() {
+#pragma unroll
+        for (int t = 0; t < S::NTILE; ++t)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[t][e] = hyp.Lambda_acc[(t * 16 + e) * 64 + lane];
     };
 
     int row;
@@ -78,14 +88,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
         const int4 rt = a.rowtab[blockIdx.x];
         row = rt.x;
         const int64_t s0 = (int64_t)(((uint64_t)(uint32_t)rt.w << 32) | (uint32_t)rt.z), s1 = s0 + rt.y;
+        if (row >= 0)
+            lambda_acc();
+        else
+            clear_acc();
         if constexpr (BF16)
             gram_bf16<KP>(a.rec + 2 * a.recoff[blockIdx.x], s1 - s0, a.other_bf16, a.shadow_stride, (char *)u,
                           (uint32_t *)rv, acc, bacc);
-        else {
-            clear_acc();
+        else
             gram_f32<KP>(a.idx + s0, vals + s0, s1 - s0, (const float *)a.other, K, rbar, u, rv,
                          sidx, acc, bacc);
-        }
         if (row < 0) {
             float *dst = pc.part + (int64_t)(-row - 1) * PW;
 #pragma unroll
@@ -98,11 +110,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
     }
 
     float *tri = u;
-    store_precision_tri<KP>(tri, acc, alpha, hyp.Lambda_acc);
+    if (pc.combine)
+        store_precision_tri<KP, true>(tri, acc, hyp.Lambda_acc);
+    else
+        store_precision_tri<KP, false>(tri, acc, hyp.Lambda_acc);
     const int ri = lane % KP;
-    // unconditional load and a multiplicative mask: as a select, the load
-    // would be moved behind a branch with its own wait
-    const float bb = fmaf(alpha, bacc, hyp.Lmu_f[ri < K ? ri : 0]) * (ri < K ? 1.0f : 0.0f);
+    // b / alpha; an unconditional load and a multiplicative mask: as a select,
+    // the load would be moved behind a branch with its own wait
+    const float bb = fmaf(hyp.Lmu_f[ri < K ? ri : 0], ialpha, bacc) * (ri < K ? 1.0f : 0.0f);
 
     float z;
     if (draws.tape_rows) {
@@ -121,7 +136,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
     __syncthreads();
 
     bool fail;
-    const float x = chol_solve<KP, BlockSync, MT>(tri, colbuf, K, bb, z, fail);
+    const float x = chol_solve<KP, BlockSync, MT>(tri, colbuf, K, bb, z * rsalpha, fail);
     if (!fail) {
         float *X = (float *)a.X;
         if (lane < KP && ri < K) X[(int64_t)row * K + ri] = x;
@@ -181,9 +196,9 @@ hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double 
 {
     if (n_entries <= 0) return hipSuccess;
     const dim3 grid((unsigned)n_entries), block(64);
-    const float fa = (float)alpha, fr = (float)rbar;
-#define BPMF_ROWS_MIXED(...) hipLaunchKernelGGL((rows_mixed_kernel<__VA_ARGS__>), grid, block, 0, s, a, K, fa, fr, hyp, \
-                                                draws, fb_list, state, draws.side, pc)
+    const float fia = (float)(1.0 / alpha), frsa = (float)(1.0 / std::sqrt(alpha)), fr = (float)rbar;
+#define BPMF_ROWS_MIXED(...) hipLaunchKernelGGL((rows_mixed_kernel<__VA_ARGS__>), grid, block, 0, s, a, K, fia, frsa, fr, \
+                                                hyp, draws, fb_list, state, draws.side, pc)
     if (KP == 64) {
         // 1: matrix-core trailing updates, 4 wavefronts per SIMD (built-in);
         // 2: vector-unit updates within each 32-column half; 3: as 1 with 3
@@ -198,8 +213,8 @@ hipError_t launch_rows_mixed(const SideArgs &a, int K, int KP, int bf16, double 
             else BPMF_ROWS_MIXED(64, false, true, 4);
         }
     } else if (KP == 32) {
-        if (bf16) hipLaunchKernelGGL((rows_mixed_kernel<32, true>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side, pc);
-        else hipLaunchKernelGGL((rows_mixed_kernel<32, false>), grid, block, 0, s, a, K, fa, fr, hyp, draws, fb_list, state, draws.side, pc);
+        if (bf16) BPMF_ROWS_MIXED(32, true);
+        else BPMF_ROWS_MIXED(32, false);
     } else {
         return hipErrorInvalidValue;
     }

@@ -602,9 +602,11 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
                 if (hi < KPm) {
                     hyp.Lambda_tri[hi * (hi + 1) / 2 + lo] = (float)x;
                     if (hyp.Lambda_acc) {
+                        // Lambda / alpha (the identity in the padding)
+                        const float xa = (r < K && cc < K) ? (float)(x / hyp.alpha) : (float)x;
                         const int q0 = lambda_acc_index(r, cc), q1 = lambda_acc_index(cc, r);
-                        if (q0 >= 0) hyp.Lambda_acc[q0] = (float)x;
-                        if (q1 >= 0) hyp.Lambda_acc[q1] = (float)x;
+                        if (q0 >= 0) hyp.Lambda_acc[q0] = xa;
+                        if (q1 >= 0) hyp.Lambda_acc[q1] = xa;
                     }
                 }
             }
@@ -668,8 +670,8 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
     if (tid == 0 && s_flag) atomicAdd((unsigned long long *)&state->nonfinite_rows, 1ull);
 }
 
-// Lambda_tri (and Lambda_acc) from Lambda_f (after a state restore, and
-// after the Normal-Wishart step for K > 64).
+// Lambda_tri from Lambda_f, and Lambda_acc from the FP64 Lambda (after a
+// state restore).
 __global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, int KP)
 {
     for (int t = threadIdx.x; t < KP * KP; t += blockDim.x) {
@@ -677,8 +679,9 @@ __global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, in
         const float v = (r < K && c < K) ? hyp.Lambda_f[r * K + c] : (r == c ? 1.0f : 0.0f);
         if (c <= r) hyp.Lambda_tri[r * (r + 1) / 2 + c] = v;
         if (hyp.Lambda_acc && KP <= 64) {
+            // Lambda / alpha from the FP64 Lambda, as the Normal-Wishart step writes it
             const int q = lambda_acc_index(r, c);
-            if (q >= 0) hyp.Lambda_acc[q] = v;
+            if (q >= 0) hyp.Lambda_acc[q] = (r < K && c < K) ? (float)(hyp.Lambda[r * K + c] / hyp.alpha) : v;
         }
     }
 }

@@ -78,8 +78,9 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
     static_assert(S::CH % 32 == 0, "the right-hand side takes 32 ratings per step");
     constexpr int NG = KP / 16;   // 16-feature groups of the right-hand side
     const int lane = threadIdx.x & 63;
-    // the accumulators start from the first chunk's products (a zero C
-    // operand, so no register is cleared); a row without ratings clears them
+    // the Gram accumulates onto acc as the caller set it up; the right-hand
+    // side's accumulators start from the first chunk's products (a zero C
+    // operand, so no register is cleared)
     floatx4 bq[NG];
     // rows 2..15 of the right-hand side's A operand read the zero words
     if (lane < S::CH / 2) rvp[S::CH + lane] = 0u;
@@ -125,21 +126,19 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
         }
     };
     // Gram tiles and right-hand side of the staged chunk (the first chunk
-    // starts every accumulator from zero)
-    const floatx16 zero16 = {};
+    // starts the right-hand side's accumulators from zero)
     const floatx4 zero4 = {};
     auto multiply_chunk = [&](auto first_chunk) {
         constexpr bool FIRST = decltype(first_chunk)::value;
 #pragma unroll
         for (int ks = 0; ks < S::CH / 16; ++ks) {
             const int off = (ks * 16 + (lane >> 5) * 8) * 2;
-            const bool fresh = FIRST && ks == 0;
             const bf16x8_t F0 = *(const bf16x8_t *)(stage + (lane & 31) * S::SB + off);
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F0, F0, fresh ? zero16 : acc[0], 0, 0, 0);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F0, F0, acc[0], 0, 0, 0);
             if constexpr (KP == 64) {
                 const bf16x8_t F1 = *(const bf16x8_t *)(stage + (32 + (lane & 31)) * S::SB + off);
-                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F0, fresh ? zero16 : acc[1], 0, 0, 0);
-                acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, fresh ? zero16 : acc[2], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F0, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, acc[2], 0, 0, 0);
             }
         }
 #pragma unroll
@@ -188,8 +187,6 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
         Sync::sync();
     }
     if (nch == 0) {
-#pragma unroll
-        for (int t = 0; t < S::NTILE; ++t) acc[t] = zero16;
 #pragma unroll
         for (int t = 0; t < NG; ++t) bq[t] = zero4;
     }
@@ -302,12 +299,13 @@ __device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc,
 // The same from Lambda stored as the padded packed triangle `lamtri` (the
 // padding entries of the Gram are zero): no index checks, and every load and
 // store uses the same offset.
-// P = Lambda + alpha G into the packed triangle `tri`, from the Gram
-// accumulators and Lambda in the same accumulator layout (`lamacc`, so each
-// load is one coalesced 256-byte access at a fixed offset).
-template <int KP>
-__device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *acc, float alpha,
-                                                    const float *lamacc)
+// P / alpha = Lambda / alpha + G into the packed triangle `tri` from the
+// Gram accumulators: ADD = false when they started from Lambda / alpha
+// (`lamacc`, the same accumulator layout), ADD = true when they hold G alone
+// and Lambda / alpha is added here (each load one coalesced 256-byte access
+// at a fixed offset).
+template <int KP, bool ADD>
+__device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *acc, const float *lamacc)
 {
     using S = RowShape<KP>;
     const int lane = threadIdx.x & 63;
@@ -319,7 +317,7 @@ __device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *
     const unsigned u16 = 16u * hh, v4 = 4u * (10u * hh + cc);
     // entries above the diagonal of a diagonal tile (cc - 4 hh > 8 j + i) go
     // to the lane's own slot in the padding after the triangle: the store
-    // stays unconditional, so the compiler cannot sink the load of Lambda
+    // stays unconditional, so the compiler cannot sink a load of Lambda
     // behind a branch of its own
     const unsigned pad4 = 4u * (KP * (KP + 1) / 2 + (unsigned)(lane % KP));
     const int above = cc - 4 * hh;
@@ -333,7 +331,8 @@ __device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *
             for (int i = 0; i < 4; ++i) {
                 const unsigned R = 32u * ta + 8u * j + i;
                 const unsigned fixed = 4u * (R * (R + 1) / 2);
-                const float v = fmaf(alpha, acc[t][4 * j + i], lamacc[(t * 16 + 4 * j + i) * 64 + lane]);
+                float v = acc[t][4 * j + i];
+                if constexpr (ADD) v += lamacc[(t * 16 + 4 * j + i) * 64 + lane];
                 unsigned off = R * u16 + v4 + 128u * tb;
                 if (t != 1) off = above > 8 * j + i ? pad4 - fixed : off;
                 *(float *)(base + off + fixed) = v;
