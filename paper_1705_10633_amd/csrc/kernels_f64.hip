@@ -688,9 +688,11 @@ hipError_t launch_stats(const StatsSides &ss, int x_is_f64, int K, hipStream_t s
     return hipErrorInvalidValue;
 }
 
-// FP32 factors with K a multiple of 4 and at most 64: lane l of a 16-lane
-// group loads features 4l..4l+3 of each of its group's 4 pairs as one
-// 16-byte load, so a group reads its 4 U rows and 4 V rows in one round trip.
+// FP32 factors with K a multiple of 4 and at most 64 NV: lane l of a 16-lane
+// group loads features 4l..4l+3 (and 64 + 4l.. when NV = 2) of each of its
+// group's 4 pairs as 16-byte loads, so a group reads its 4 U rows and 4 V rows
+// in one round trip.
+template <int NV>
 __global__ __launch_bounds__(256) void predict_vec4_kernel(const float *U, const float *V, int K, double rbar,
                                                            int64_t n, const int32_t *rows, const int32_t *cols,
                                                            double *out, double *accum, const DevState *state,
@@ -699,24 +701,38 @@ __global__ __launch_bounds__(256) void predict_vec4_kernel(const float *U, const
     constexpr int PP = 4;
     const int64_t t0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4) * PP;
     const int l = threadIdx.x & 15;
-    const bool lane_on = 4 * l < K;
-    const int fo = lane_on ? 4 * l : 0;  // clamped: the load stays unmasked
-    float4 a[PP], b[PP];
+    bool lane_on[NV];
+    int fo[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        lane_on[v] = 64 * v + 4 * l < K;
+        fo[v] = lane_on[v] ? 64 * v + 4 * l : 0;  // clamped: the loads stay unmasked
+    }
+    float4 a[PP][NV], b[PP][NV];
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
         const int64_t t = t0 + q < n ? t0 + q : n - 1;
-        a[q] = *(const float4 *)(U + (int64_t)rows[t] * K + fo);
-        b[q] = *(const float4 *)(V + (int64_t)cols[t] * K + fo);
+        const float *ur = U + (int64_t)rows[t] * K, *vr = V + (int64_t)cols[t] * K;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            a[q][v] = *(const float4 *)(ur + fo[v]);
+            b[q][v] = *(const float4 *)(vr + fo[v]);
+        }
     }
     double p[PP];
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
         double s = 0.0;
-        s = fma((double)a[q].x, (double)b[q].x, s);
-        s = fma((double)a[q].y, (double)b[q].y, s);
-        s = fma((double)a[q].z, (double)b[q].z, s);
-        s = fma((double)a[q].w, (double)b[q].w, s);
-        p[q] = lane_on ? s : 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double sv = 0.0;
+            sv = fma((double)a[q][v].x, (double)b[q][v].x, sv);
+            sv = fma((double)a[q][v].y, (double)b[q][v].y, sv);
+            sv = fma((double)a[q][v].z, (double)b[q][v].z, sv);
+            sv = fma((double)a[q][v].w, (double)b[q][v].w, sv);
+            s += lane_on[v] ? sv : 0.0;
+        }
+        p[q] = s;
     }
 #pragma unroll
     for (int q = 0; q < PP; ++q)
@@ -741,9 +757,14 @@ hipError_t launch_predict(const void *U, const void *V, int x_is_f64, int K, dou
     if (x_is_f64)
         hipLaunchKernelGGL(predict_kernel<double>, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
                            (const double *)U, (const double *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
-    else if (K % 4 == 0 && K <= 64 && ((uintptr_t)U % 16 == 0) && ((uintptr_t)V % 16 == 0))
-        hipLaunchKernelGGL(predict_vec4_kernel, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
-                           (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
+    else if (K % 4 == 0 && K <= 128 && ((uintptr_t)U % 16 == 0) && ((uintptr_t)V % 16 == 0)) {
+        if (K <= 64)
+            hipLaunchKernelGGL(predict_vec4_kernel<1>, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
+                               (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
+        else
+            hipLaunchKernelGGL(predict_vec4_kernel<2>, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
+                               (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
+    }
     else
         hipLaunchKernelGGL(predict_kernel<float>, dim3(grid_for((n + 3) / 4 * 16, 256)), dim3(256), 0, s,
                            (const float *)U, (const float *)V, K, rbar, n, rows, cols, out, accum, state, burnin);
