@@ -218,7 +218,7 @@ def main():
         print(json.dumps({"calib_copy_bytes": 1 << 30, "copies": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the sampler runs on one GPU only; --gpus must be 1"}))
         log("bench.py: the sampler and its kernels run on one GPU; multi-GPU sharding is not built")
         sys.exit(2)
 
