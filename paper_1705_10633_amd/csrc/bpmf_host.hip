@@ -371,6 +371,7 @@ bpmf_status bpmf_init(bpmf_ctx **out, const bpmf_ratings *R, const bpmf_params *
         c->hyp[sd].Lmu_f = c->at<float>(off.lmuf[sd]);
         c->hyp[sd].Lambda_tri = c->at<float>(off.lamt[sd]);
         c->hyp[sd].alpha = p->alpha;
+        c->hyp[sd].acc16 = (p->precision == BPMF_BF16 && padded_k(K) == 64) ? 1 : 0;
         c->hyp[sd].Lambda_acc = (mixed_supported(K, p->precision) && p->precision != BPMF_FP64 && K <= 64)
                                     ? c->at<float>(off.lamacc[sd]) : nullptr;
         c->hyp[sd].Lchol = (mixed_supported(K, p->precision) && p->precision != BPMF_FP64 && K <= 64)

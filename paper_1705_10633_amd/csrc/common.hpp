@@ -52,6 +52,7 @@ struct HyperDev {
     // 4 (l / 32) + e % 4, c = 32 b + l % 32 (identity in the padding); the
     // row kernel's accumulators start from it
     float *Lambda_acc;
+    int32_t acc16;   // Lambda_acc in the 16 x 16 tile layout (BF16, KP = 64)
     double alpha;    // the sampler's alpha
     // chol(Lambda) in FP32 for the rank-one row paths (K <= 64), or NULL:
     // KP x KP row-major (lower; identity in the padding), then KP floats each
@@ -152,13 +153,22 @@ hipError_t launch_rows_f64(const SideArgs &a, int K, double alpha, double rbar,
 hipError_t launch_rows_mixed128(const SideArgs &a, int K, double alpha, double rbar, HyperDev hyp,
                                 DrawSrc draws, int32_t *fb_list, DevState *state, hipStream_t s);
 // Pieces of heavy rows (see rows_mixed_kernel): per piece, the partial Gram
-// tiles in accumulator layout plus the right-hand side, floats per piece:
+// tiles in accumulator layout plus the right-hand side, floats per piece (the
+// stride; the 16 x 16 tile layout uses 40 x 64 + 64 of them):
 __host__ __device__ constexpr int piece_floats(int KP) { return (KP == 64 ? 3 : 1) * 16 * 64 + 64; }
 
-// Position of Lambda[r][c] (r >= c, both < 64) in the accumulator layout of
-// HyperDev::Lambda_acc (-1 for an upper tile).
-__host__ __device__ inline int lambda_acc_index(int r, int c)
+// Position of Lambda[r][c] (both < 64) in the accumulator layout of
+// HyperDev::Lambda_acc (-1 for an upper tile): lower 32 x 32 tiles, or with
+// g16 the ten lower 16 x 16 tiles (the K <= 64 BF16 row kernel's layout for
+// KP = 64; see GramAcc).
+__host__ __device__ inline int lambda_acc_index(int r, int c, bool g16)
 {
+    if (g16) {
+        const int a = r >> 4, b = c >> 4;
+        if (a < b) return -1;
+        const int rr = r & 15;
+        return (4 * (a * (a + 1) / 2 + b) + (rr & 3)) * 64 + 16 * (rr >> 2) + (c & 15);
+    }
     const int ta = r >> 5, tb = c >> 5;
     if (ta < tb) return -1;
     const int t = ta == 0 ? 0 : (tb == 0 ? 1 : 2);

@@ -54,19 +54,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
     // and z the solves give the same x.  A row's Gram accumulators start from
     // Lambda / alpha (in their own layout); a piece's, and a combined heavy
     // row's, from zero.
-    floatx16 acc[S::NTILE];
+    // BF16 at KP = 64: the ten lower 16 x 16 tiles (GramAcc)
+    using Acc = GramAcc<KP, BF16 && KP == 64>;
+    Acc acc;
     float bacc = 0.0f;
     auto clear_acc = [&]() {
 #pragma unroll
-        for (int t = 0; t < S::NTILE; ++t)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
+        for (int i = 0; i < Acc::N; ++i) acc.set(i, 0.0f);
     };
     auto lambda_acc = [&]() {
 #pragma unroll
-        for (int t = 0; t < S::NTILE; ++t)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) acc[t][e] = hyp.Lambda_acc[(t * 16 + e) * 64 + lane];
+        for (int i = 0; i < Acc::N; ++i) acc.set(i, hyp.Lambda_acc[i * 64 + lane]);
     };
 
     int row;
@@ -78,10 +76,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
         for (int p = ct.y; p < ct.y + ct.z; ++p) {
             const float *src = pc.part + (int64_t)p * PW;
 #pragma unroll
-            for (int t = 0; t < S::NTILE; ++t)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) acc[t][e] += src[(t * 16 + e) * 64 + lane];
-            bacc += src[S::NTILE * 16 * 64 + lane];
+            for (int i = 0; i < Acc::N; ++i) acc.set(i, acc.get(i) + src[i * 64 + lane]);
+            bacc += src[Acc::N * 64 + lane];
         }
     } else {
         // {row, rating count, first rating (low, high word)}; row < 0: piece -row - 1
@@ -97,14 +93,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W))) void
                           (uint32_t *)rv, acc, bacc);
         else
             gram_f32<KP>(a.idx + s0, vals + s0, s1 - s0, (const float *)a.other, K, rbar, u, rv,
-                         sidx, acc, bacc);
+                         sidx, acc.t, bacc);
         if (row < 0) {
             float *dst = pc.part + (int64_t)(-row - 1) * PW;
 #pragma unroll
-            for (int t = 0; t < S::NTILE; ++t)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) dst[(t * 16 + e) * 64 + lane] = acc[t][e];
-            dst[S::NTILE * 16 * 64 + lane] = bacc;
+            for (int i = 0; i < Acc::N; ++i) dst[i * 64 + lane] = acc.get(i);
+            dst[Acc::N * 64 + lane] = bacc;
             return;
         }
     }

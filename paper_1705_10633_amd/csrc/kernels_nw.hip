@@ -604,7 +604,7 @@ __global__ __launch_bounds__(256) void nw_compact_kernel(NwSide side0, NwSide si
                     if (hyp.Lambda_acc) {
                         // Lambda / alpha (the identity in the padding)
                         const float xa = (r < K && cc < K) ? (float)(x / hyp.alpha) : (float)x;
-                        const int q0 = lambda_acc_index(r, cc), q1 = lambda_acc_index(cc, r);
+                        const int q0 = lambda_acc_index(r, cc, hyp.acc16), q1 = lambda_acc_index(cc, r, hyp.acc16);
                         if (q0 >= 0) hyp.Lambda_acc[q0] = xa;
                         if (q1 >= 0) hyp.Lambda_acc[q1] = xa;
                     }
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(256) void lambda_tri_kernel(HyperDev hyp, int K, in
         if (c <= r) hyp.Lambda_tri[r * (r + 1) / 2 + c] = v;
         if (hyp.Lambda_acc && KP <= 64) {
             // Lambda / alpha from the FP64 Lambda, as the Normal-Wishart step writes it
-            const int q = lambda_acc_index(r, c);
+            const int q = lambda_acc_index(r, c, hyp.acc16);
             if (q >= 0) hyp.Lambda_acc[q] = (r < K && c < K) ? (float)(hyp.Lambda[r * K + c] / hyp.alpha) : v;
         }
     }

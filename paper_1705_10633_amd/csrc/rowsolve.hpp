@@ -36,6 +36,34 @@ struct RowShape {
     static constexpr int NTILE = KP == 64 ? 3 : 1;
 };
 
+// Gram accumulators of a row, element i of N per lane (the layout the
+// Normal-Wishart step writes Lambda / alpha in: HyperDev::Lambda_acc).
+//  * G16 = false: lower 32 x 32 tiles, element 16 t + e of lane l is entry
+//    (32 a + 8 (e / 4) + 4 (l / 32) + e % 4, 32 b + l % 32) of tile t
+//    ((0,0), (1,0), (1,1));
+//  * G16 = true (KP = 64, BF16 Gram on v_mfma_f32_16x16x32_bf16): the ten
+//    lower 16 x 16 tiles, t = a (a + 1) / 2 + b, element 4 t + v of lane l is
+//    entry (16 a + 4 (l / 16) + v, 16 b + l % 16).
+template <int KP, bool G16>
+struct GramAcc;
+template <int KP>
+struct GramAcc<KP, false> {
+    static constexpr bool g16 = false;
+    static constexpr int N = RowShape<KP>::NTILE * 16;
+    floatx16 t[RowShape<KP>::NTILE];
+    __device__ __forceinline__ float get(int i) const { return t[i >> 4][i & 15]; }
+    __device__ __forceinline__ void set(int i, float v) { t[i >> 4][i & 15] = v; }
+};
+template <int KP>
+struct GramAcc<KP, true> {
+    static_assert(KP == 64, "16 x 16 Gram tiles for KP = 64");
+    static constexpr bool g16 = true;
+    static constexpr int N = 40;
+    floatx4 t[10];
+    __device__ __forceinline__ float get(int i) const { return t[i >> 2][i & 3]; }
+    __device__ __forceinline__ void set(int i, float v) { t[i >> 2][i & 3] = v; }
+};
+
 __device__ __forceinline__ float readlane_f(float v, int lane)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -69,9 +97,9 @@ struct WaveSync {
 // features 16t..16t+15, so C[0][f] and C[1][f] collect the hi and lo sums of
 // feature 16t + f.  `rvp` holds the chunk's CH / 2 packed hi pairs, its CH / 2
 // lo pairs and CH / 2 zero words (3 CH / 2 words).
-template <int KP, class Sync = BlockSync>
+template <int KP, class Sync = BlockSync, class Acc>
 __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const uint16_t *src, int stride,
-                                          char *stage, uint32_t *rvp, floatx16 *acc, float &bacc)
+                                          char *stage, uint32_t *rvp, Acc &acc, float &bacc)
 {
     using S = RowShape<KP>;
     static_assert(S::CH == bf16_chunk(KP), "records are padded to the kernel's chunk");
@@ -130,15 +158,34 @@ __device__ __forceinline__ void gram_bf16(const uint4 *rec, int64_t nnz, const u
     const floatx4 zero4 = {};
     auto multiply_chunk = [&](auto first_chunk) {
         constexpr bool FIRST = decltype(first_chunk)::value;
+        if constexpr (Acc::g16) {
+            // ten lower 16 x 16 tiles: lane l's operand for feature block b
+            // (features 16 b + l % 16, 8 ratings from 8 (l / 16)) serves as
+            // both A and B
 #pragma unroll
-        for (int ks = 0; ks < S::CH / 16; ++ks) {
-            const int off = (ks * 16 + (lane >> 5) * 8) * 2;
-            const bf16x8_t F0 = *(const bf16x8_t *)(stage + (lane & 31) * S::SB + off);
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F0, F0, acc[0], 0, 0, 0);
-            if constexpr (KP == 64) {
-                const bf16x8_t F1 = *(const bf16x8_t *)(stage + (32 + (lane & 31)) * S::SB + off);
-                acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F0, acc[1], 0, 0, 0);
-                acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, acc[2], 0, 0, 0);
+            for (int ks = 0; ks < S::CH / 32; ++ks) {
+                bf16x8_t F[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    F[b] = *(const bf16x8_t *)(stage + (16 * b + lane % 16) * S::SB + (ks * 32 + (lane / 16) * 8) * 2);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b <= a; ++b)
+                        acc.t[a * (a + 1) / 2 + b] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(F[a], F[b], acc.t[a * (a + 1) / 2 + b], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < S::CH / 16; ++ks) {
+                const int off = (ks * 16 + (lane >> 5) * 8) * 2;
+                const bf16x8_t F0 = *(const bf16x8_t *)(stage + (lane & 31) * S::SB + off);
+                acc.t[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F0, F0, acc.t[0], 0, 0, 0);
+                if constexpr (KP == 64) {
+                    const bf16x8_t F1 = *(const bf16x8_t *)(stage + (32 + (lane & 31)) * S::SB + off);
+                    acc.t[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F0, acc.t[1], 0, 0, 0);
+                    acc.t[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F1, F1, acc.t[2], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
@@ -304,39 +351,64 @@ __device__ __forceinline__ void store_precision(float *tri, const floatx16 *acc,
 // (`lamacc`, the same accumulator layout), ADD = true when they hold G alone
 // and Lambda / alpha is added here (each load one coalesced 256-byte access
 // at a fixed offset).
-template <int KP, bool ADD>
-__device__ __forceinline__ void store_precision_tri(float *tri, const floatx16 *acc, const float *lamacc)
+template <int KP, bool ADD, class Acc>
+__device__ __forceinline__ void store_precision_tri(float *tri, const Acc &acc, const float *lamacc)
 {
-    using S = RowShape<KP>;
     const int lane = threadIdx.x & 63;
-    const int hh = lane >> 5, cc = lane & 31;
-    // Entry (r, c) of tile (ta, tb), r = R + 4 hh with R = 32 ta + 8 j + i,
-    // c = 32 tb + cc, sits at r (r + 1) / 2 + c = R (R + 1) / 2 + 4 hh R +
-    // (10 hh + c).  In bytes: a per-lane part R * 16 hh + 4 (10 hh + c) and
-    // a compile-time part 4 R (R + 1) / 2 that goes into the store's offset.
-    const unsigned u16 = 16u * hh, v4 = 4u * (10u * hh + cc);
-    // entries above the diagonal of a diagonal tile (cc - 4 hh > 8 j + i) go
-    // to the lane's own slot in the padding after the triangle: the store
-    // stays unconditional, so the compiler cannot sink a load of Lambda
-    // behind a branch of its own
+    // entries above the diagonal of a diagonal tile go to the lane's own slot
+    // in the padding after the triangle: the store stays unconditional, so
+    // the compiler cannot sink a load of Lambda behind a branch of its own
     const unsigned pad4 = 4u * (KP * (KP + 1) / 2 + (unsigned)(lane % KP));
-    const int above = cc - 4 * hh;
     char *base = (char *)tri;
+    if constexpr (Acc::g16) {
+        // Entry (r, c) of 16 x 16 tile (a, b), r = R + 4 q with R = 16 a + v
+        // and q = lane / 16, c = 16 b + lane % 16, sits at r (r + 1) / 2 + c =
+        // R (R + 1) / 2 + 4 q R + 8 q^2 + 2 q + c: in bytes a per-lane part
+        // R * 16 q + 4 (8 q^2 + 2 q + lane % 16) and a compile-time part
+        // 4 R (R + 1) / 2 + 64 b that goes into the store's offset.
+        const int q = lane >> 4, cl = lane & 15;
+        const unsigned q16 = 16u * q, lc = 4u * (8u * q * q + 2u * q + cl);
+        const int above = cl - 4 * q;  // c - r + v in a diagonal tile
 #pragma unroll
-    for (int t = 0; t < S::NTILE; ++t) {
-        const int ta = (t == 0) ? 0 : 1, tb = (t == 2) ? 1 : 0;
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int b = 0; b <= a; ++b)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const unsigned R = 32u * ta + 8u * j + i;
-                const unsigned fixed = 4u * (R * (R + 1) / 2);
-                float v = acc[t][4 * j + i];
-                if constexpr (ADD) v += lamacc[(t * 16 + 4 * j + i) * 64 + lane];
-                unsigned off = R * u16 + v4 + 128u * tb;
-                if (t != 1) off = above > 8 * j + i ? pad4 - fixed : off;
-                *(float *)(base + off + fixed) = v;
-            }
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 4 * (a * (a + 1) / 2 + b) + v;
+                    const unsigned R = 16u * a + v;
+                    const unsigned fixed = 4u * (R * (R + 1) / 2) + 64u * b;
+                    float x = acc.get(i);
+                    if constexpr (ADD) x += lamacc[i * 64 + lane];
+                    unsigned off = R * q16 + lc;
+                    if (a == b) off = above > v ? pad4 - fixed : off;
+                    *(float *)(base + off + fixed) = x;
+                }
+    } else {
+        using S = RowShape<KP>;
+        const int hh = lane >> 5, cc = lane & 31;
+        // Entry (r, c) of tile (ta, tb), r = R + 4 hh with R = 32 ta + 8 j + i,
+        // c = 32 tb + cc, sits at r (r + 1) / 2 + c = R (R + 1) / 2 + 4 hh R +
+        // (10 hh + c).  In bytes: a per-lane part R * 16 hh + 4 (10 hh + c) and
+        // a compile-time part 4 R (R + 1) / 2 that goes into the store's offset.
+        const unsigned u16 = 16u * hh, v4 = 4u * (10u * hh + cc);
+        const int above = cc - 4 * hh;  // above the diagonal: cc - 4 hh > 8 j + i
+#pragma unroll
+        for (int t = 0; t < S::NTILE; ++t) {
+            const int ta = (t == 0) ? 0 : 1, tb = (t == 2) ? 1 : 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const unsigned R = 32u * ta + 8u * j + i;
+                    const unsigned fixed = 4u * (R * (R + 1) / 2);
+                    float x = acc.get(t * 16 + 4 * j + i);
+                    if constexpr (ADD) x += lamacc[(t * 16 + 4 * j + i) * 64 + lane];
+                    unsigned off = R * u16 + v4 + 128u * tb;
+                    if (t != 1) off = above > 8 * j + i ? pad4 - fixed : off;
+                    *(float *)(base + off + fixed) = x;
+                }
+        }
     }
 }
 
